@@ -1,0 +1,232 @@
+/*
+ * liblbm -- semi-Lagrangian off-lattice Boltzmann time step on AMD Instinct
+ * MI355X (gfx950).  C ABI.
+ *
+ * The method is the one of Wilde, Kraemer, Bedrunka, Reith, Foysi, "Cubature
+ * rules for weakly and fully compressible off-lattice Boltzmann methods"
+ * (arXiv 2101.03982), Sec. 3:
+ *   1. streaming: every population f_i is interpolated at its departure point
+ *      x - xi_i dt (eq. sl_streaming).  This library interpolates on a uniform
+ *      grid with a tensor product of 1D Lagrange polynomials through n
+ *      neighbouring nodes per axis (the n nodes around the departure point for
+ *      even n; for odd n the n nodes centred on the nearest node, the arrival
+ *      side winning an exact tie);
+ *   2. moments: rho = sum f_i, rho u = sum xi_i f_i (eqs. density, momentum)
+ *      and, in the compressible model, 2 rho C_v theta =
+ *      sum(|xi_i - u|^2 f_i / T0 + g_i) with T0 = c_s^2;
+ *   3. equilibrium: the Hermite expansion of App. A truncated at order N,
+ *      g^eq = theta (2 C_v - D) f^eq;
+ *   4. BGK relaxation f <- f - (f - f^eq)/tau (lattice Boltzmann equation),
+ *      tau = 1/2 + (tau_ref - 1/2)/(rho theta) in the compressible model
+ *      (tau = mu/(c_s^2 dt P) + 1/2 with P = rho theta).
+ * Velocity sets: D2Q9, D2Q19, D2Q25, D3Q13, D3Q21, D3Q27, D3V27, D3Q45
+ * (Table tab:sets, Tables tab:d3q13 and tab:d3q21, Apps. C-E).
+ *
+ * Conventions shared by every call:
+ *  - Return value: LBM_OK (0) or a negative lbm_status.  No call throws or
+ *    aborts; lbm_strerror() names the code and lbm_last_error() gives the
+ *    message of the most recent failure on the calling thread.
+ *  - Population buffers are caller-owned device memory in the layout
+ *    [A*Q][nz][ny][nx], x fastest, f populations then g populations (A = 2
+ *    only in the compressible model), element type by storage:
+ *    LBM_F64 double, LBM_F32 float, LBM_BF16DEV bfloat16 and LBM_F16DEV
+ *    IEEE half holding the deviation f_i - r_i from the reference
+ *    r_i = w_i (f) or (2 C_v - D) w_i (g).  lbm_state_bytes() gives the size.
+ *  - Macroscopic fields (rho, u, theta) are device arrays of the compute type:
+ *    double for LBM_F64 storage, float otherwise; u is [D][nz][ny][nx] in the
+ *    physical units of dx and dt.
+ *  - Device work is enqueued on the context's stream and returns at once;
+ *    only lbm_moments() (and lbm_sync()) wait.  Asynchronous kernel failures
+ *    surface in the next synchronizing call as LBM_EHIP.  A context is not
+ *    thread-safe; use one context per stream.
+ *  - Population index order: rows of the printed tables in order, sign
+ *    patterns of the non-zero components in lexicographic order with + before
+ *    -, first component outermost; "(cyc)" rows expand to (a,b,c), (c,a,b),
+ *    (b,c,a); product sets enumerate 1D nodes (0, +a, -a, +b, -b), first axis
+ *    outermost.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lbm_status {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,        /* bad argument: null pointer, size, range, grid too small */
+  LBM_ENOMEM = -2,        /* device or host allocation failed */
+  LBM_EHIP = -3,          /* HIP runtime error (launch or asynchronous fault) */
+  LBM_EUNSUPPORTED = -4,  /* combination not built: set/order/stencil/storage */
+  LBM_EDIVERGED = -5      /* NaN, rho <= 0 or theta <= 0 found by lbm_moments */
+} lbm_status;
+
+typedef enum lbm_set {
+  LBM_D2Q9 = 0, LBM_D2Q19 = 1, LBM_D2Q25 = 2, LBM_D3Q13 = 3,
+  LBM_D3Q21 = 4, LBM_D3Q27 = 5, LBM_D3V27 = 6, LBM_D3Q45 = 7
+} lbm_set;
+
+typedef enum lbm_storage {
+  LBM_F64 = 0,      /* double populations, double arithmetic */
+  LBM_F32 = 1,      /* float populations, float arithmetic */
+  LBM_BF16DEV = 2,  /* bfloat16 deviations f - r, float arithmetic */
+  LBM_F16DEV = 3    /* IEEE half deviations f - r, float arithmetic */
+} lbm_storage;
+
+typedef enum lbm_boundary {
+  LBM_PERIODIC = 0,     /* node indices wrap around */
+  LBM_EXTRAPOLATE = 1   /* zeroth-order extrapolation: indices clamp to the edge */
+} lbm_boundary;
+
+typedef struct lbm_options {
+  int32_t storage;       /* lbm_storage */
+  int32_t stencil;       /* Lagrange nodes per axis n, 1..5 */
+  int32_t compressible;  /* 0: f only, theta = 1; 1: f and g (Sec. 3) */
+  int32_t boundary[3];   /* lbm_boundary per axis x, y, z */
+  int32_t energy_f64;    /* deviation storage, compressible: sum the energy moment in FP64 */
+  int32_t reserved;
+  double dx;             /* grid spacing (> 0) */
+  double dt;             /* time step (> 0) */
+  double cs;             /* speed of sound the set is scaled to; <= 0: the table's own */
+  double gamma;          /* heat capacity ratio (compressible; C_v = 1/(gamma - 1)) */
+  void *stream;          /* hipStream_t for all work of the context; NULL = null stream */
+} lbm_options;
+
+typedef struct lbm_diag {
+  double mass;           /* sum over cells of rho */
+  double momentum[3];    /* sum over cells of rho u */
+  double ke;             /* mean over cells of |u|^2 / 2 (Sec. 4.2, unweighted) */
+  double energy;         /* sum over cells of sum_i (|xi_i|^2 f_i / T0 + g_i) / 2 */
+  double min_rho;        /* smallest rho */
+  double min_theta;      /* smallest theta (1 in the weakly compressible model) */
+  int32_t nonfinite;     /* number of cells whose rho, u or theta is not finite */
+  int32_t reserved;
+} lbm_diag;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Fills opt with defaults: F32 storage, n = 4, periodic, dx = dt = 1,
+ * cs = table's own, gamma = 1.4, null stream. */
+void lbm_default_options(lbm_options *opt);
+
+/* Creates a context for velocity set `set` on the grid grid[0] x grid[1] x
+ * grid[2] (nx, ny, nz; nz must be 1 for the 2D sets), relaxation time `tau`
+ * (at rho theta = 1 in the compressible model; must exceed 1/2) and Hermite
+ * truncation order `order` (App. A; 2 <= order and 2 * order <= degree of the
+ * set, so that the equilibrium's moments up to order N are exact, Sec. 2).
+ * Computes the per-direction stencil (offsets and Lagrange weights) on the
+ * host in FP64 and uploads it; allocates small device scratch for reductions.
+ * The grid must hold the stencil: along every periodic axis of N nodes
+ * every first-node offset o satisfies -N <= o and o + n <= N + 1.  The context uses the current HIP
+ * device.  On failure *out is NULL.  Ownership: the caller destroys the
+ * context with lbm_destroy(). */
+int lbm_create(lbm_ctx **out, int32_t set, const int64_t grid[3], double tau, int32_t order,
+               const lbm_options *opt);
+
+/* Releases the context's own device and host memory (never the caller's
+ * buffers).  Waits for the context's stream first.  NULL is accepted. */
+int lbm_destroy(lbm_ctx *ctx);
+
+/* Bytes of one population buffer: A * Q * nx * ny * nz * element size. */
+size_t lbm_state_bytes(const lbm_ctx *ctx);
+
+/* Hands the context two caller-owned device buffers of lbm_state_bytes()
+ * bytes each (ping-pong pair; they must not overlap).  buf0 becomes the
+ * current state.  The caller keeps ownership and must keep them alive while
+ * the context uses them. */
+int lbm_bind(lbm_ctx *ctx, void *buf0, void *buf1);
+
+/* Device pointer of the buffer that holds the current state. */
+void *lbm_state(lbm_ctx *ctx);
+
+/* Writes f = f^eq(rho, u, theta) (and g = g^eq) into the current buffer.
+ * rho [cells], u [D][cells] (physical units), theta [cells] or NULL
+ * (theta = 1), all device arrays of the compute type. */
+int lbm_init_equilibrium(lbm_ctx *ctx, const void *rho, const void *u, const void *theta);
+
+/* Advances the bound state by n >= 0 time steps (stream, then collide); each
+ * step reads the current buffer and writes the other one, which then becomes
+ * current.  n = 0 does nothing. */
+int lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* One time step from src to dst (caller device buffers of lbm_state_bytes(),
+ * not overlapping); the bound pair is neither used nor changed. */
+int lbm_step_into(lbm_ctx *ctx, const void *src, void *dst);
+
+/* Per-cell rho, u, theta of `state` (NULL: the current buffer) into the
+ * optional device arrays rho/u/theta (any may be NULL), and global
+ * diagnostics into *diag (may be NULL).  The stored state is post-collision;
+ * its rho, rho u and energy equal the pre-collision ones because the collision
+ * conserves them (Sec. 3).  Synchronizes the context's stream.  Returns
+ * LBM_EDIVERGED (with *diag filled) if a cell holds a non-finite value,
+ * rho <= 0 or theta <= 0. */
+int lbm_moments(lbm_ctx *ctx, const void *state, void *rho, void *u, void *theta, lbm_diag *diag);
+
+/* Waits for the context's stream; reports asynchronous HIP errors. */
+int lbm_sync(lbm_ctx *ctx);
+
+/* Changes the stream used by later calls. */
+int lbm_set_stream(lbm_ctx *ctx, void *stream);
+
+/* ---- Adjoint (reverse-mode derivative of the time step; not in the paper).
+ * Weakly compressible model with LBM_F64 or LBM_F32 storage only
+ * (LBM_EUNSUPPORTED otherwise).  One time step is f' = C(S f) with S the
+ * linear streaming and C the per-cell collision.  All arrays are device
+ * arrays of the compute type in the population layout [Q][cells]. ---- */
+
+/* nu = J_C(S f_prev)^T lam : adjoint of the collision of the step that
+ * starts from f_prev, applied to lam = dL/df' (the step's output). */
+int lbm_adjoint_collide(lbm_ctx *ctx, const void *f_prev, const void *lam, void *nu);
+
+/* dst = S src : streaming alone, without the collision (forward stencil),
+ * for diagnostics and tests; same availability as the adjoint calls. */
+int lbm_stream(lbm_ctx *ctx, const void *src, void *dst);
+
+/* lam = S^T nu : adjoint of streaming (a gather with mirrored offsets and
+ * reversed weights), giving dL/df_prev. */
+int lbm_adjoint_stream(lbm_ctx *ctx, const void *nu, void *lam);
+
+/* nu_out = J_C(S f_prev)^T S^T nu_in : one fused reverse step.  With
+ * nu_in = nu_{t+1} (the collision adjoint of step t+1) and f_prev = f_{t-1}
+ * it returns nu_t; the chain starts with lbm_adjoint_collide and ends with
+ * lbm_adjoint_stream. */
+int lbm_adjoint_step(lbm_ctx *ctx, const void *f_prev, const void *nu_in, void *nu_out);
+
+/* lam = dK/df for the mean kinetic energy K = <|u|^2/2> of state f. */
+int lbm_ke_adjoint(lbm_ctx *ctx, const void *f, void *lam);
+
+/* grad_u = (d f^eq(rho, u, 1)/d u)^T lam0, per cell: the gradient with
+ * respect to the initial velocity through lbm_init_equilibrium. */
+int lbm_init_equilibrium_adjoint(lbm_ctx *ctx, const void *rho, const void *u, const void *lam0,
+                                 void *grad_u);
+
+/* ---- Host-only helpers (no GPU needed) ---- */
+
+/* The per-direction stencil the kernels use, computed on the host: for every
+ * population i and axis a, offsets[3*i + a] is the offset of the first
+ * stencil node from the arrival node and weights[(3*i + a)*n + k] the weight
+ * of node k, for a set scaled to speed of sound cs (<= 0: the table's own)
+ * with time step dt and spacing dx.  An axis along which xi_i has no
+ * component gets offset 0 and the single weight 1 followed by zeros.  The
+ * weights are exact FP64 Lagrange weights (not the quantized ones the kernels
+ * use).  Arrays hold Q*3 and Q*3*n entries. */
+int lbm_stencil(int32_t set, double dt, double dx, double cs, int32_t n, int32_t *offsets, double *weights);
+
+/* The library's velocity set table: Q, D, degree, table speed of sound,
+ * weights w[Q] and abscissae xi[Q][3] in table units. */
+int lbm_set_table(int32_t set, int32_t *Q, int32_t *D, int32_t *degree, double *cs, double *w, double *xi);
+
+const char *lbm_strerror(int status);
+const char *lbm_last_error(void);
+
+/* Version of the ABI described by this header. */
+int32_t lbm_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

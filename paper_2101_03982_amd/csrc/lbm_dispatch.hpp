@@ -1,0 +1,62 @@
+// Host-side view of the kernels built for one velocity set: launchers looked
+// up by (stencil length, Hermite order, number of population arrays, storage).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+using StepLaunch = hipError_t (*)(const KParams&, hipStream_t);
+using CellLaunch = hipError_t (*)(const CellParams&, hipStream_t);
+
+struct Kernels {
+  StepLaunch mode[4] = {nullptr, nullptr, nullptr, nullptr};  // indexed by Mode
+  CellLaunch init = nullptr;
+  CellLaunch moments = nullptr;     // writes partials; grid = moments_blocks(ncell)
+  CellLaunch ke_adjoint = nullptr;
+  CellLaunch init_adjoint = nullptr;
+};
+
+constexpr int MOMENT_BLOCKS = 1024;
+
+// Which combinations are compiled.  Every set gets the forward step for each
+// stencil length 2..5 (1: on-lattice copy, D2Q9 and D3Q27 only) and each
+// Hermite order with 2N <= degree; the compressible model (two arrays) with
+// N = 4; 16-bit deviation storage on the 3D sets; the adjoint modes with
+// FP64/FP32 storage in the weakly compressible model.
+template <int SET, int NS, int N, int A, int ST>
+constexpr bool combo_built() {
+  constexpr int D = Set<SET>::D;
+  constexpr int deg = Set<SET>::degree;
+  if (2 * N > deg) return false;
+  if (A == 2 && N != 4) return false;
+  if (NS == 1 && !(SET == D2Q9 || SET == D3Q27)) return false;
+  if ((ST == ST_BF16 || ST == ST_F16) && D != 3) return false;
+  return true;
+}
+
+template <int SET, int NS, int N, int A, int ST, int MODE>
+constexpr bool mode_built() {
+  if (!combo_built<SET, NS, N, A, ST>()) return false;
+  if (MODE == MODE_STEP) return true;
+  return A == 1 && N <= 3 && (ST == ST_F64 || ST == ST_F32);
+}
+
+// Which (set, storage, stencil length) parts exist as compiled units.
+template <int SET, int ST, int NS>
+constexpr bool part_exists() {
+  if (NS == 1 && !(SET == D2Q9 || SET == D3Q27)) return false;
+  if ((ST == ST_BF16 || ST == ST_F16) && Set<SET>::D != 3) return false;
+  return true;
+}
+
+template <int SET, int ST, int NS>
+bool find_kernels_part(int order, int arrays, Kernels* out);
+
+// Launcher table of a set (defined in the host library, dispatching to the
+// per-set instantiation units).
+bool find_kernels(int set, int ns, int order, int arrays, int storage, Kernels* out);
+
+}  // namespace lbm

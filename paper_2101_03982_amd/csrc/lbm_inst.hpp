@@ -1,0 +1,91 @@
+// Instantiation of the built kernels of one (velocity set, storage, stencil
+// length) and their launcher table.  Each generated unit under _build/
+// instantiates one such part, so that the parts compile in parallel.
+#pragma once
+
+#include "lbm_dispatch.hpp"
+
+namespace lbm {
+
+template <class F, int... I>
+inline void host_for_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+inline void host_for(F&& f) {
+  host_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+template <int SET, int NS, int N, int A, int ST, int MODE>
+hipError_t launch_step(const KParams& p, hipStream_t s) {
+  using R = typename StoreT<ST>::real;
+  constexpr int D = Set<SET>::D;
+  constexpr int RO = cells_per_thread<D, Set<SET>::Q, A, int(sizeof(R)), MODE>();
+  dim3 grid;
+  grid.x = (p.n[0] + 63) / 64;
+  if (D == 3) {
+    grid.y = (p.n[1] + 3) / 4;
+    grid.z = (p.n[2] + RO - 1) / RO;
+  } else {
+    grid.y = (p.n[1] + 4 * RO - 1) / (4 * RO);
+    grid.z = 1;
+  }
+  hipLaunchKernelGGL((sl_kernel<SET, NS, N, A, ST, MODE>), grid, dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+inline dim3 cell_grid(int64_t ncell) { return dim3(unsigned((ncell + 255) / 256)); }
+
+template <int SET, int N, int A, int ST>
+hipError_t launch_init(const CellParams& p, hipStream_t s) {
+  hipLaunchKernelGGL((init_kernel<SET, N, A, ST>), cell_grid(p.ncell), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+template <int SET, int A, int ST>
+hipError_t launch_moments(const CellParams& p, hipStream_t s) {
+  hipLaunchKernelGGL((moments_kernel<SET, A, ST>), dim3(MOMENT_BLOCKS), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+template <int SET, int ST>
+hipError_t launch_ke_adjoint(const CellParams& p, hipStream_t s) {
+  hipLaunchKernelGGL((ke_adjoint_kernel<SET, ST>), cell_grid(p.ncell), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+template <int SET, int N, int ST>
+hipError_t launch_init_adjoint(const CellParams& p, hipStream_t s) {
+  hipLaunchKernelGGL((init_adjoint_kernel<SET, N, ST>), cell_grid(p.ncell), dim3(256), 0, s, p);
+  return hipGetLastError();
+}
+
+template <int SET, int ST, int NS>
+bool find_kernels_part(int order, int arrays, Kernels* out) {
+  bool found = false;
+  host_for<3>([&](auto nc) {
+    constexpr int N = decltype(nc)::value + 2;
+    host_for<2>([&](auto ac) {
+      constexpr int A = decltype(ac)::value + 1;
+      if constexpr (combo_built<SET, NS, N, A, ST>()) {
+        if (order == N && arrays == A) {
+          found = true;
+          *out = Kernels{};
+          out->mode[MODE_STEP] = &launch_step<SET, NS, N, A, ST, MODE_STEP>;
+          if constexpr (mode_built<SET, NS, N, A, ST, MODE_ADJ_COLLIDE>()) {
+            out->mode[MODE_ADJ_COLLIDE] = &launch_step<SET, NS, N, A, ST, MODE_ADJ_COLLIDE>;
+            out->mode[MODE_ADJ_STEP] = &launch_step<SET, NS, N, A, ST, MODE_ADJ_STEP>;
+            out->mode[MODE_ADJ_STREAM] = &launch_step<SET, NS, N, A, ST, MODE_ADJ_STREAM>;
+            out->ke_adjoint = &launch_ke_adjoint<SET, ST>;
+            out->init_adjoint = &launch_init_adjoint<SET, N, ST>;
+          }
+          out->init = &launch_init<SET, N, A, ST>;
+          out->moments = &launch_moments<SET, A, ST>;
+        }
+      }
+    });
+  });
+  return found;
+}
+
+}  // namespace lbm

@@ -1,0 +1,914 @@
+// Fused semi-Lagrangian stream + collide kernels for gfx950 (MI355X).
+//
+// One kernel template serves every velocity set, stencil length, Hermite
+// order, storage type and mode (forward step, collision adjoint, fused reverse
+// step, transposed streaming).  The set is a template parameter, so every
+// population's abscissa is a compile-time constant: zero components drop out
+// of the moment and equilibrium arithmetic, and an axis along which a
+// population does not move costs neither a halo nor an interpolation pass.
+//
+// Work decomposition (3D).  A 256-thread block owns a 64 x 4 x RO tile of
+// cells: lane = x, wave = y, and each thread holds RO cells along z.  For each
+// population (unrolled at compile time) the block
+//   A. loads, per (x, y) column of the population's source region (the tile
+//      shifted by the stencil's first-node offset, widened by n - 1 along every
+//      moving axis), the RO + n - 1 values along z from HBM, interpolates along
+//      z in registers and writes RO values per column to LDS;
+//   B. interpolates along y in LDS (one thread per (z, x) column);
+//   C. interpolates along x from LDS into the thread's registers.
+// A population that moves along z only never touches LDS.  After the last
+// population each thread holds all interpolated populations of its RO cells,
+// forms the moments, the Hermite equilibrium in its scalar closed form and
+// the BGK update in registers, and stores coalesced along x.
+// 2D: the same with y in the role of z and the four waves splitting y.
+//
+// The stencil (first-node offsets and Lagrange weights per population and
+// axis) is computed on the host and read through uniform (scalar) loads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <type_traits>
+#include <utility>
+
+#include "lbm_sets.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// Storage types
+// ---------------------------------------------------------------------------
+
+enum Storage : int { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2, ST_F16 = 3 };
+
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+// round to nearest even; NaN stays NaN
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+
+template <int S> struct StoreT;
+template <> struct StoreT<ST_F64> {
+  using elem = double; using real = double; static constexpr bool dev = false;
+  static __device__ __forceinline__ real ld(const elem* p) { return *p; }
+  static __device__ __forceinline__ void st(elem* p, real v) { *p = v; }
+};
+template <> struct StoreT<ST_F32> {
+  using elem = float; using real = float; static constexpr bool dev = false;
+  static __device__ __forceinline__ real ld(const elem* p) { return *p; }
+  static __device__ __forceinline__ void st(elem* p, real v) { *p = v; }
+};
+template <> struct StoreT<ST_BF16> {
+  using elem = uint16_t; using real = float; static constexpr bool dev = true;
+  static __device__ __forceinline__ real ld(const elem* p) { return bf16_to_f32(*p); }
+  static __device__ __forceinline__ void st(elem* p, real v) { *p = f32_to_bf16(v); }
+};
+template <> struct StoreT<ST_F16> {
+  using elem = _Float16; using real = float; static constexpr bool dev = true;
+  static __device__ __forceinline__ real ld(const elem* p) { return float(*p); }
+  static __device__ __forceinline__ void st(elem* p, real v) { *p = _Float16(v); }
+};
+
+// ---------------------------------------------------------------------------
+// Compile-time loop
+// ---------------------------------------------------------------------------
+
+template <class F, int... I>
+__device__ __forceinline__ void sfor_impl(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  sfor_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// ---------------------------------------------------------------------------
+// Kernel parameters
+// ---------------------------------------------------------------------------
+
+enum Mode : int {
+  MODE_STEP = 0,        // f' = C(S f)
+  MODE_ADJ_COLLIDE = 1, // nu = J_C(S f)^T lam
+  MODE_ADJ_STEP = 2,    // nu' = J_C(S f)^T (S^T nu)
+  MODE_ADJ_STREAM = 3   // lam = S^T nu
+};
+
+struct KParams {
+  const void* src;     // populations interpolated with the forward stencil (f)
+  const void* src2;    // second input: lam (ADJ_COLLIDE) or nu (ADJ_STEP / ADJ_STREAM)
+  void* dst;
+  const int* off;      // [Q][3] first-node offsets, forward stencil
+  const void* wts;     // [Q][3][NS] weights (compute type), forward stencil
+  const int* off_t;    // transposed stencil (adjoint modes)
+  const void* wts_t;
+  int n[3];            // nx, ny, nz
+  int bc[3];           // 0 periodic, 1 extrapolate (clamp)
+  int64_t pstride;     // cells per population
+  double omega;        // 1 / tau (weakly compressible)
+  double tau_m_half;   // tau_ref - 1/2 (compressible)
+  double cv2mD;        // 2 C_v - D
+  double inv2cv;       // 1 / (2 C_v)
+  double sw;           // sum_i w_i of the stored table
+  double swx[3];       // sum_i w_i xh_i
+  double swX;          // sum_i w_i |xh_i|^2
+  double e64;          // nonzero: compressible energy moment summed in FP64
+};
+
+// Cells per thread along the register (outer) axis.
+template <int D, int Q, int A, int RBYTES, int MODE>
+constexpr int cells_per_thread() {
+  constexpr int vals = A * Q * (RBYTES / 4) * ((MODE == MODE_ADJ_STEP || MODE == MODE_ADJ_COLLIDE) ? 2 : 1);
+  if (D == 2) return vals <= 40 ? 4 : (vals <= 80 ? 2 : 1);
+  return vals <= 30 ? 4 : (vals <= 60 ? 2 : 1);
+}
+
+// Node index on the grid: periodic wrap (valid for i in [-n, 2n)) or, on an
+// extrapolating axis, the nearest boundary node.  Branch-free.
+__device__ __forceinline__ int wrap_idx(int i, int n, int bc) {
+  int w = i + ((i < 0) ? n : 0);
+  w -= (w >= n) ? n : 0;
+  const int c = min(max(i, 0), n - 1);
+  return bc ? c : w;
+}
+
+// ---------------------------------------------------------------------------
+// Interpolation of one population of A arrays into registers
+// ---------------------------------------------------------------------------
+
+template <int SET, int NS, int A, int ST, int RO>
+struct Tile {
+  using S = Set<SET>;
+  using TR = StoreT<ST>;
+  using R = typename TR::real;
+  using E = typename TR::elem;
+  static constexpr int D = S::D;
+  static constexpr int TX = 64;
+  static constexpr int NW = 4;                       // waves per block
+  static constexpr int H = NS - 1;
+  static constexpr int PX = TX + H;                  // widest LDS row
+  static constexpr int PM = (D == 3) ? NW + H : NW;  // rows per outer plane in P
+  static constexpr int TOUT = (D == 3) ? RO : NW * RO;  // outer extent of the tile
+  static constexpr int PSZ = A * RO * PM * PX;       // one P buffer
+  static constexpr int TSZ = (D == 3) ? A * RO * NW * PX : 1;
+};
+
+// Per-thread / per-block geometry
+struct Geo {
+  int x0, m0, o0;        // tile origin: inner (x), middle (y, 3D), outer (z or y)
+  int nx, nm, no;        // extents along inner, middle, outer
+  int bcx, bcm, bco;
+  int sm, so;            // element strides of middle and outer axes
+  int vx, vm, vo;        // valid extents of the tile along each axis
+  int lane, w, tid;
+};
+
+// Element at a 32-bit element offset from a per-population base pointer
+// (the host guarantees that one population spans less than 4 GiB), so that
+// loads use a scalar base and a 32-bit vector offset.
+template <typename E>
+__device__ __forceinline__ const E* at(const E* base, int e) {
+  return reinterpret_cast<const E*>(reinterpret_cast<const char*>(base) + uint32_t(e) * uint32_t(sizeof(E)));
+}
+template <typename E>
+__device__ __forceinline__ E* at(E* base, int e) {
+  return reinterpret_cast<E*>(reinterpret_cast<char*>(base) + uint32_t(e) * uint32_t(sizeof(E)));
+}
+
+// Interpolate population q (all A arrays) of `src` with stencil (off, wts)
+// into out[a][r], using the LDS buffers P and T of the current parity.
+template <int SET, int NS, int A, int ST, int RO, int q>
+__device__ __forceinline__ void interp_pop(const Geo& g, const typename StoreT<ST>::elem* __restrict__ src,
+                                           int64_t pstride, const int* __restrict__ off,
+                                           const typename StoreT<ST>::real* __restrict__ wts,
+                                           typename StoreT<ST>::real* P, typename StoreT<ST>::real* T,
+                                           typename StoreT<ST>::real (&out)[A][RO]) {
+  using TL = Tile<SET, NS, A, ST, RO>;
+  using S = typename TL::S;
+  using TR = StoreT<ST>;
+  using R = typename TR::real;
+  using E = typename TR::elem;
+  constexpr int D = S::D;
+  constexpr int Q = S::Q;
+  constexpr bool mx = NS > 1 && S::moves(q, 0);
+  constexpr bool mm = NS > 1 && D == 3 && S::moves(q, 1);
+  constexpr bool mo = NS > 1 && S::moves(q, D - 1);
+  constexpr int HX = mx ? NS - 1 : 0;
+  constexpr int HM = mm ? NS - 1 : 0;
+  constexpr int HO = mo ? NS - 1 : 0;
+  constexpr int KX = mx ? NS : 1, KM = mm ? NS : 1, KO = mo ? NS : 1;
+  constexpr int axm = 1, axo = D - 1;
+
+  const int ox = off[3 * q + 0];
+  const int om = (D == 3) ? off[3 * q + axm] : 0;
+  const int oo = off[3 * q + axo];
+  R wx[KX], wm[KM], wo[KO];
+#pragma unroll
+  for (int k = 0; k < KX; ++k) wx[k] = mx ? wts[(3 * q + 0) * NS + k] : R(1);
+#pragma unroll
+  for (int k = 0; k < KM; ++k) wm[k] = mm ? wts[(3 * q + axm) * NS + k] : R(1);
+#pragma unroll
+  for (int k = 0; k < KO; ++k) wo[k] = mo ? wts[(3 * q + axo) * NS + k] : R(1);
+
+  const E* base[A];
+#pragma unroll
+  for (int a = 0; a < A; ++a) base[a] = src + int64_t(a * Q + q) * pstride;
+
+  // outer-axis interpolation of RO + HO loaded values
+  auto outer = [&](const R (&v)[A][RO + HO], R (&res)[A][RO]) {
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+#pragma unroll
+      for (int r = 0; r < RO; ++r) {
+        if constexpr (KO == 1) {
+          res[a][r] = v[a][r];
+        } else {
+          R s = v[a][r] * wo[0];
+#pragma unroll
+          for (int k = 1; k < KO; ++k) s = fma(wo[k], v[a][r + k], s);
+          res[a][r] = s;
+        }
+      }
+  };
+
+  if constexpr (!mx && !mm) {
+    // direct path: each thread loads its own column
+    const int gx = wrap_idx(g.x0 + min(g.lane, g.vx - 1) + ox, g.nx, g.bcx);
+    int col = gx, ob = g.o0, vo = g.vo;
+    if constexpr (D == 3) {
+      col += wrap_idx(g.m0 + min(g.w, g.vm - 1) + om, g.nm, g.bcm) * g.sm;
+    } else {
+      ob = g.o0 + min(g.w * RO, g.vo - 1);  // a dead segment reads in-bounds rows
+      vo = max(1, min(RO, g.vo - g.w * RO));
+    }
+    R v[A][RO + HO];
+#pragma unroll
+    for (int r = 0; r < RO + HO; ++r) {
+      const int e = wrap_idx(ob + oo + min(r, vo - 1 + HO), g.no, g.bco) * g.so + col;
+#pragma unroll
+      for (int a = 0; a < A; ++a) v[a][r] = TR::ld(at(base[a], e));
+    }
+    outer(v, out);
+  } else {
+    constexpr int CX = TL::TX + HX;                      // columns along x
+    constexpr int CM = (D == 3) ? TL::NW + HM : TL::NW;  // along middle (3D) or segments (2D)
+    constexpr int NCOL = CX * CM;
+    constexpr int ROUNDS = (NCOL + 255) / 256;
+    constexpr int PX = TL::PX, PM = TL::PM;
+    // ---- phase A: HBM -> registers (outer interpolation) -> LDS.  All loads
+    // of all rounds are issued before the first one is used.
+    int col[ROUNDS], ob[ROUNDS], vo[ROUNDS], slot[ROUNDS];
+#pragma unroll
+    for (int rr = 0; rr < ROUNDS; ++rr) {
+      const int c = min(g.tid + 256 * rr, NCOL - 1);
+      const int xs = c % CX, ms = c / CX;
+      slot[rr] = ms * PX + xs;
+      col[rr] = wrap_idx(g.x0 + ox + min(xs, g.vx - 1 + HX), g.nx, g.bcx);
+      if constexpr (D == 3) {
+        col[rr] += wrap_idx(g.m0 + om + min(ms, g.vm - 1 + HM), g.nm, g.bcm) * g.sm;
+        ob[rr] = g.o0;
+        vo[rr] = g.vo;
+      } else {
+        ob[rr] = g.o0 + min(ms * RO, g.vo - 1);  // a dead segment reads in-bounds rows
+        vo[rr] = max(1, min(RO, g.vo - ms * RO));
+      }
+    }
+    R v[ROUNDS][A][RO + HO];
+#pragma unroll
+    for (int rr = 0; rr < ROUNDS; ++rr) {
+      if (NCOL % 256 == 0 || rr + 1 < ROUNDS || g.tid + 256 * rr < NCOL) {
+#pragma unroll
+        for (int r = 0; r < RO + HO; ++r) {
+          const int e = wrap_idx(ob[rr] + oo + min(r, vo[rr] - 1 + HO), g.no, g.bco) * g.so + col[rr];
+#pragma unroll
+          for (int a = 0; a < A; ++a) v[rr][a][r] = TR::ld(at(base[a], e));
+        }
+      }
+    }
+#pragma unroll
+    for (int rr = 0; rr < ROUNDS; ++rr) {
+      if (NCOL % 256 == 0 || rr + 1 < ROUNDS || g.tid + 256 * rr < NCOL) {
+        R res[A][RO];
+        outer(v[rr], res);
+#pragma unroll
+        for (int a = 0; a < A; ++a)
+#pragma unroll
+          for (int r = 0; r < RO; ++r) P[(a * RO + r) * PM * PX + slot[rr]] = res[a][r];
+      }
+    }
+    __syncthreads();
+    const R* X = P;  // rows the x pass reads: [a][r][row][x], row = wave
+    if constexpr (mm) {
+      // ---- phase B: y interpolation in LDS, one thread per (a, r, x) column
+      constexpr int NB = A * RO * CX;
+#pragma unroll
+      for (int c0 = 0; c0 < NB; c0 += 256) {
+        const int c = c0 + g.tid;
+        if (NB % 256 == 0 || c < NB) {
+          const int xs = c % CX, ar = c / CX;
+          R colv[TL::NW + HM];
+#pragma unroll
+          for (int m = 0; m < TL::NW + HM; ++m) colv[m] = P[(ar * PM + m) * PX + xs];
+#pragma unroll
+          for (int m = 0; m < TL::NW; ++m) {
+            R s = colv[m] * wm[0];
+#pragma unroll
+            for (int k = 1; k < KM; ++k) s = fma(wm[k], colv[m + k], s);
+            T[(ar * TL::NW + m) * PX + xs] = s;
+          }
+        }
+      }
+      __syncthreads();
+      X = T;
+    }
+    // ---- phase C: x interpolation from LDS into registers
+    constexpr int XR = mm ? TL::NW : PM;  // rows per (a, r) plane of X
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+#pragma unroll
+      for (int r = 0; r < RO; ++r) {
+        const R* row = X + ((a * RO + r) * XR + g.w) * PX + g.lane;
+        if constexpr (KX == 1) {
+          out[a][r] = row[0];
+        } else {
+          R s = row[0] * wx[0];
+#pragma unroll
+          for (int k = 1; k < KX; ++k) s = fma(wx[k], row[k], s);
+          out[a][r] = s;
+        }
+      }
+  }
+  // Finish the interpolation here: without this the compiler sinks the last
+  // pass to the collision and keeps every population's n raw taps alive.
+#pragma unroll
+  for (int a = 0; a < A; ++a)
+#pragma unroll
+    for (int r = 0; r < RO; ++r) asm volatile("" : "+v"(out[a][r]));
+}
+
+// Whether population q uses LDS (needs the block-wide passes).
+template <int SET, int NS, int q>
+constexpr bool uses_lds() {
+  using S = Set<SET>;
+  return NS > 1 && (S::moves(q, 0) || (S::D == 3 && S::moves(q, 1)));
+}
+
+template <int SET, int NS, int q>
+constexpr int lds_rank() {  // number of LDS-using populations before q
+  int c = 0;
+  if constexpr (q > 0) c = lds_rank<SET, NS, q - 1>() + (uses_lds<SET, NS, q - 1>() ? 1 : 0);
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// Equilibrium polynomial P(a, U, eta, X) = f^eq / (w rho), minus 1
+// (App. A contracted with T0 = c_s^2; a = xh . u~, U = |u~|^2, X = |xh|^2,
+// eta = theta - 1; the eta terms vanish in the weakly compressible model).
+// ---------------------------------------------------------------------------
+
+template <int N, int D, bool COMP, typename R>
+__device__ __forceinline__ R peq_minus1(R a, R U, R eta, R X) {
+  R a2 = a * a;
+  R s = a + R(0.5) * (a2 - U);
+  if constexpr (COMP) s += R(0.5) * eta * (X - R(D));
+  if constexpr (N >= 3) {
+    R t = a * (a2 - R(3) * U);
+    if constexpr (COMP) t += R(3) * eta * a * (X - R(D + 2));
+    s += t * R(1.0 / 6.0);
+  }
+  if constexpr (N >= 4) {
+    R t = a2 * a2 - R(6) * a2 * U + R(3) * U * U;
+    if constexpr (COMP) {
+      t += R(6) * eta * ((X - R(D + 4)) * a2 - (X - R(D + 2)) * U);
+      t += R(3) * eta * eta * (X * X - R(2 * (D + 2)) * X + R(D * (D + 2)));
+    }
+    s += t * R(1.0 / 24.0);
+  }
+  return s;
+}
+
+// Derivatives of P with respect to a and U (weakly compressible, eta = 0).
+template <int N, typename R>
+__device__ __forceinline__ void peq_derivs(R a, R U, R& P, R& Pa, R& PU) {
+  R a2 = a * a;
+  P = R(1) + a + R(0.5) * (a2 - U);
+  Pa = R(1) + a;
+  PU = R(-0.5);
+  if constexpr (N >= 3) {
+    P += a * (a2 - R(3) * U) * R(1.0 / 6.0);
+    Pa += R(0.5) * (a2 - U);
+    PU -= R(0.5) * a;
+  }
+  if constexpr (N >= 4) {
+    P += (a2 * a2 - R(6) * a2 * U + R(3) * U * U) * R(1.0 / 24.0);
+    Pa += a * (a2 - R(3) * U) * R(1.0 / 6.0);
+    PU += R(0.25) * (U - a2);
+  }
+}
+
+template <typename R>
+struct Kahan {
+  R s = R(0), c = R(0);
+  __device__ __forceinline__ void add(R v) {
+    R y = v - c;
+    R t = s + y;
+    c = (t - s) - y;
+    s = t;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// The fused kernel
+// ---------------------------------------------------------------------------
+
+template <int SET, int NS, int N, int A, int ST, int MODE>
+__global__ __launch_bounds__(256) void sl_kernel(KParams p) {
+  using S = Set<SET>;
+  using TR = StoreT<ST>;
+  using R = typename TR::real;
+  using E = typename TR::elem;
+  constexpr int D = S::D;
+  constexpr int Q = S::Q;
+  constexpr bool DEV = TR::dev;
+  constexpr bool COMP = (A == 2);
+  constexpr int RO = cells_per_thread<D, Q, A, int(sizeof(R)), MODE>();
+  using TL = Tile<SET, NS, A, ST, RO>;
+
+  __shared__ R P_lds[2][TL::PSZ];
+  __shared__ R T_lds[2][TL::TSZ];
+
+  Geo g;
+  g.tid = threadIdx.x;
+  g.lane = threadIdx.x & 63;
+  g.w = threadIdx.x >> 6;
+  g.nx = p.n[0];
+  g.bcx = p.bc[0];
+  g.x0 = blockIdx.x * TL::TX;
+  g.vx = min(TL::TX, g.nx - g.x0);
+  if constexpr (D == 3) {
+    g.nm = p.n[1]; g.no = p.n[2];
+    g.bcm = p.bc[1]; g.bco = p.bc[2];
+    g.sm = p.n[0]; g.so = p.n[0] * p.n[1];
+    g.m0 = blockIdx.y * TL::NW;
+    g.o0 = blockIdx.z * RO;
+    g.vm = min(TL::NW, g.nm - g.m0);
+    g.vo = min(RO, g.no - g.o0);
+  } else {
+    g.nm = 1; g.no = p.n[1];
+    g.bcm = 0; g.bco = p.bc[1];
+    g.sm = 0; g.so = p.n[0];
+    g.m0 = 0;
+    g.o0 = blockIdx.y * TL::TOUT;
+    g.vm = 1;
+    g.vo = min(TL::TOUT, g.no - g.o0);
+  }
+
+  const E* __restrict__ src = static_cast<const E*>(p.src);
+  const R* __restrict__ wts = static_cast<const R*>(p.wts);
+  const R* __restrict__ wts_t = static_cast<const R*>(p.wts_t);
+
+  // interpolated populations of this thread's RO cells
+  R ft[A * Q][RO];
+  // second interpolated / local input for the adjoint modes
+  constexpr bool TWO = (MODE == MODE_ADJ_STEP || MODE == MODE_ADJ_COLLIDE);
+  R lam[TWO ? Q : 1][RO];
+
+  if constexpr (MODE != MODE_ADJ_STREAM) {
+    static_for<Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      constexpr int buf = lds_rank<SET, NS, q>() & 1;
+      R o[A][RO];
+      interp_pop<SET, NS, A, ST, RO, q>(g, src, p.pstride, p.off, wts, P_lds[buf], T_lds[buf], o);
+#pragma unroll
+      for (int a = 0; a < A; ++a)
+#pragma unroll
+        for (int r = 0; r < RO; ++r) ft[a * Q + q][r] = o[a][r];
+    });
+  }
+  if constexpr (MODE == MODE_ADJ_STEP || MODE == MODE_ADJ_STREAM) {
+    // S^T applied to src2 with the transposed stencil; src2 is of the compute type
+    const E* __restrict__ src2 = static_cast<const E*>(p.src2);
+    constexpr int base = (MODE == MODE_ADJ_STREAM) ? 0 : 1;
+    static_for<Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      constexpr int buf = (lds_rank<SET, NS, q>() + base * lds_rank<SET, NS, Q>()) & 1;
+      R o[1][RO];
+      interp_pop<SET, NS, 1, ST, RO, q>(g, src2, p.pstride, p.off_t, wts_t, P_lds[buf], T_lds[buf], o);
+#pragma unroll
+      for (int r = 0; r < RO; ++r) {
+        if constexpr (MODE == MODE_ADJ_STREAM) ft[q][r] = o[0][r];
+        else lam[q][r] = o[0][r];
+      }
+    });
+  }
+
+  // cell coordinates of this thread's RO cells
+  const int xi = g.x0 + g.lane;
+  int mi = 0, obase = g.o0, ovalid = g.vo;
+  if constexpr (D == 3) {
+    mi = g.m0 + g.w;
+  } else {
+    obase = g.o0 + g.w * RO;
+    ovalid = min(RO, g.vo - g.w * RO);
+  }
+  const bool live = (g.lane < g.vx) && (D == 2 || g.w < g.vm) && ovalid > 0;
+  if (!live) return;
+
+  E* __restrict__ dst = static_cast<E*>(p.dst);
+  const E* __restrict__ lam_in = static_cast<const E*>(p.src2);
+
+#pragma unroll
+  for (int r = 0; r < RO; ++r) {
+    if (r >= ovalid) break;
+    const int64_t cell = (D == 3) ? (int64_t(obase + r) * g.nm + mi) * g.nx + xi : int64_t(obase + r) * g.nx + xi;
+
+    if constexpr (MODE == MODE_ADJ_STREAM) {
+      static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        TR::st(dst + int64_t(q) * p.pstride + cell, ft[q][r]);
+      });
+    } else {
+
+    // ---- moments (Sec. 3): rho, j~ = sum xh f (and energy sums)
+    R rho, jx = R(0), jy = R(0), jz = R(0);
+    R Ef = R(0), G = R(0);
+    double Ed = 0.0;
+    if constexpr (DEV) {
+      Kahan<R> kr, kx, ky, kz, ke, kg;
+      static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const R d = ft[q][r];
+        kr.add(d);
+        if constexpr (S::moves(q, 0)) kx.add(R(S::xh(q, 0)) * d);
+        if constexpr (S::moves(q, 1)) ky.add(R(S::xh(q, 1)) * d);
+        if constexpr (D == 3 && S::moves(q, 2)) kz.add(R(S::xh(q, 2)) * d);
+        if constexpr (COMP) {
+          constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
+          if (p.e64 != 0.0) Ed = fma(X, double(d), Ed);
+          else ke.add(R(X) * d);
+          kg.add(ft[Q + q][r]);
+        }
+      });
+      rho = R(p.sw) + kr.s;
+      jx = R(p.swx[0]) + kx.s;
+      jy = R(p.swx[1]) + ky.s;
+      jz = R(p.swx[2]) + kz.s;
+      if constexpr (COMP) {
+        Ed += p.swX;
+        Ef = R(p.swX) + ke.s;
+        G = R(p.cv2mD * p.sw) + kg.s;
+      }
+    } else {
+      rho = R(0);
+      static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const R f = ft[q][r];
+        rho += f;
+        if constexpr (S::moves(q, 0)) jx = fma(R(S::xh(q, 0)), f, jx);
+        if constexpr (S::moves(q, 1)) jy = fma(R(S::xh(q, 1)), f, jy);
+        if constexpr (D == 3 && S::moves(q, 2)) jz = fma(R(S::xh(q, 2)), f, jz);
+        if constexpr (COMP) {
+          constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
+          if constexpr (X != 0.0) Ef = fma(R(X), f, Ef);
+          G += ft[Q + q][r];
+        }
+      });
+    }
+    const R inv_rho = R(1) / rho;
+    const R ux = jx * inv_rho, uy = jy * inv_rho, uz = (D == 3) ? jz * inv_rho : R(0);
+    const R U = ux * ux + uy * uy + uz * uz;
+
+    if constexpr (MODE == MODE_STEP) {
+      R omega = R(p.omega), theta = R(1), eta = R(0);
+      if constexpr (COMP) {
+        // 2 rho C_v theta = sum |xh - u~|^2 f + sum g = E_f - rho U + G
+        if constexpr (DEV) {
+          if (p.e64 != 0.0) {
+            const double th = (Ed - double(rho) * double(U) + double(G)) * p.inv2cv / double(rho);
+            theta = R(th);
+            eta = R(th - 1.0);
+          } else {
+            theta = (Ef - rho * U + G) * R(p.inv2cv) * inv_rho;
+            eta = theta - R(1);
+          }
+        } else {
+          theta = (Ef - rho * U + G) * R(p.inv2cv) * inv_rho;
+          eta = theta - R(1);
+        }
+        // tau = 1/2 + (tau_ref - 1/2) / (rho theta)
+        const R tau = R(0.5) + R(p.tau_m_half) / (rho * theta);
+        omega = R(1) / tau;
+      }
+      const R om1 = R(1) - omega;
+      const R cv2 = R(p.cv2mD);
+      static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
+        R a = R(0);
+        if constexpr (S::moves(q, 0)) a = fma(R(S::xh(q, 0)), ux, a);
+        if constexpr (S::moves(q, 1)) a = fma(R(S::xh(q, 1)), uy, a);
+        if constexpr (D == 3 && S::moves(q, 2)) a = fma(R(S::xh(q, 2)), uz, a);
+        const R pm1 = peq_minus1<N, D, COMP, R>(a, U, eta, R(X));
+        const R w = R(S::w(q));
+        R feq_dev;  // f^eq - w (DEV) or f^eq
+        if constexpr (DEV) feq_dev = w * fma(rho - R(1), R(1) + pm1, pm1);
+        else feq_dev = w * rho * (R(1) + pm1);
+        const R fo = fma(omega, feq_dev, om1 * ft[q][r]);
+        TR::st(dst + int64_t(q) * p.pstride + cell, fo);
+        if constexpr (COMP) {
+          R geq;
+          if constexpr (DEV) geq = cv2 * fma(theta, feq_dev, eta * w);
+          else geq = cv2 * theta * feq_dev;
+          const R go = fma(omega, geq, om1 * ft[Q + q][r]);
+          TR::st(dst + int64_t(Q + q) * p.pstride + cell, go);
+        }
+      });
+    } else {
+      // adjoint of the weakly compressible collision at this cell
+      R lm[Q];
+      if constexpr (MODE == MODE_ADJ_COLLIDE) {
+        static_for<Q>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          lm[q] = TR::ld(lam_in + int64_t(q) * p.pstride + cell);
+        });
+      } else {
+        static_for<Q>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          lm[q] = lam[q][r];
+        });
+      }
+      const R omega = R(p.omega);
+      R v0 = R(0), vx = R(0), vy = R(0), vz = R(0);
+      static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        R a = R(0);
+        if constexpr (S::moves(q, 0)) a = fma(R(S::xh(q, 0)), ux, a);
+        if constexpr (S::moves(q, 1)) a = fma(R(S::xh(q, 1)), uy, a);
+        if constexpr (D == 3 && S::moves(q, 2)) a = fma(R(S::xh(q, 2)), uz, a);
+        R Pq, Pa, PU;
+        peq_derivs<N, R>(a, U, Pq, Pa, PU);
+        const R lw = lm[q] * R(S::w(q));
+        v0 = fma(lw, Pq - Pa * a - R(2) * PU * U, v0);
+        const R c2 = R(2) * PU;
+        if constexpr (S::moves(q, 0)) vx = fma(lw, Pa * R(S::xh(q, 0)), vx);
+        if constexpr (S::moves(q, 1)) vy = fma(lw, Pa * R(S::xh(q, 1)), vy);
+        if constexpr (D == 3 && S::moves(q, 2)) vz = fma(lw, Pa * R(S::xh(q, 2)), vz);
+        // the 2 P_U u~ part of d f^eq / d j~ is common to every direction
+        vx = fma(lw * c2, ux, vx);
+        vy = fma(lw * c2, uy, vy);
+        if constexpr (D == 3) vz = fma(lw * c2, uz, vz);
+      });
+      const R om1 = R(1) - omega;
+      static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        R m = v0;
+        if constexpr (S::moves(q, 0)) m = fma(R(S::xh(q, 0)), vx, m);
+        if constexpr (S::moves(q, 1)) m = fma(R(S::xh(q, 1)), vy, m);
+        if constexpr (D == 3 && S::moves(q, 2)) m = fma(R(S::xh(q, 2)), vz, m);
+        const R mu = fma(om1, lm[q], omega * m);
+        TR::st(dst + int64_t(q) * p.pstride + cell, mu);
+      });
+    }
+    }  // not ADJ_STREAM
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Per-cell kernels: equilibrium initialisation, moments, loss / init adjoints
+// ---------------------------------------------------------------------------
+
+struct CellParams {
+  const void* f;      // populations (storage type)
+  void* out_f;        // populations out (init)
+  const void* rho;    // [cells] compute type
+  const void* u;      // [D][cells]
+  const void* theta;  // [cells] or null
+  const void* lam;    // [Q][cells] compute type
+  void* out_rho;
+  void* out_u;
+  void* out_theta;
+  double* partial;    // [blocks][8]
+  int64_t ncell;
+  double cs;          // u = cs * u~
+  double cv2mD, inv2cv, sw, swX, swx[3];
+  double scale;       // 1 / ncell (KE adjoint)
+};
+
+template <int SET, int N, int A, int ST>
+__global__ __launch_bounds__(256) void init_kernel(CellParams p) {
+  using S = Set<SET>;
+  using TR = StoreT<ST>;
+  using R = typename TR::real;
+  using E = typename TR::elem;
+  constexpr int D = S::D, Q = S::Q;
+  constexpr bool COMP = (A == 2);
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= p.ncell) return;
+  const R* rho_p = static_cast<const R*>(p.rho);
+  const R* u_p = static_cast<const R*>(p.u);
+  const R* th_p = static_cast<const R*>(p.theta);
+  E* out = static_cast<E*>(p.out_f);
+  const R rho = rho_p[e];
+  const R inv_cs = R(1.0 / p.cs);
+  const R ux = u_p[e] * inv_cs, uy = u_p[p.ncell + e] * inv_cs;
+  const R uz = (D == 3) ? u_p[2 * p.ncell + e] * inv_cs : R(0);
+  const R U = ux * ux + uy * uy + uz * uz;
+  const R theta = (COMP && th_p) ? th_p[e] : R(1);
+  const R eta = theta - R(1);
+  static_for<Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
+    const R a = R(S::xh(q, 0)) * ux + R(S::xh(q, 1)) * uy + R(S::xh(q, 2)) * uz;
+    const R pm1 = peq_minus1<N, D, COMP, R>(a, U, eta, R(X));
+    const R w = R(S::w(q));
+    R fe;
+    if constexpr (TR::dev) fe = w * fma(rho - R(1), R(1) + pm1, pm1);
+    else fe = w * rho * (R(1) + pm1);
+    TR::st(out + int64_t(q) * p.ncell + e, fe);
+    if constexpr (COMP) {
+      R ge;
+      if constexpr (TR::dev) ge = R(p.cv2mD) * fma(theta, fe, eta * w);
+      else ge = R(p.cv2mD) * theta * fe;
+      TR::st(out + int64_t(Q + q) * p.ncell + e, ge);
+    }
+  });
+}
+
+// Per-cell moments of a stored state plus block partial sums:
+// [0] mass, [1..3] momentum, [4] sum |u|^2/2, [5] energy, [6] min rho,
+// [7] min theta, [8] count of non-finite cells.  Grid-stride loop.
+constexpr int NPART = 9;
+
+template <int SET, int A, int ST>
+__global__ __launch_bounds__(256) void moments_kernel(CellParams p) {
+  using S = Set<SET>;
+  using TR = StoreT<ST>;
+  using R = typename TR::real;
+  using E = typename TR::elem;
+  constexpr int D = S::D, Q = S::Q;
+  constexpr bool COMP = (A == 2);
+  const E* f = static_cast<const E*>(p.f);
+  R* orho = static_cast<R*>(p.out_rho);
+  R* ou = static_cast<R*>(p.out_u);
+  R* oth = static_cast<R*>(p.out_theta);
+  double acc[NPART] = {0, 0, 0, 0, 0, 0, 1e300, 1e300, 0};
+  for (int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x; e < p.ncell; e += int64_t(gridDim.x) * 256) {
+    double rho = 0, jx = 0, jy = 0, jz = 0, Ef = 0, G = 0;
+    static_for<Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      double v = double(TR::ld(f + int64_t(q) * p.ncell + e));
+      if constexpr (TR::dev) v += S::w(q);
+      rho += v;
+      jx += S::xh(q, 0) * v;
+      jy += S::xh(q, 1) * v;
+      jz += S::xh(q, 2) * v;
+      constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
+      Ef += X * v;
+      if constexpr (COMP) {
+        double gv = double(TR::ld(f + int64_t(Q + q) * p.ncell + e));
+        if constexpr (TR::dev) gv += p.cv2mD * S::w(q);
+        G += gv;
+      }
+    });
+    const double ux = jx / rho, uy = jy / rho, uz = jz / rho;
+    const double U = ux * ux + uy * uy + uz * uz;
+    const double theta = COMP ? (Ef - rho * U + G) * p.inv2cv / rho : 1.0;
+    const double cs = p.cs;
+    if (orho) orho[e] = R(rho);
+    if (ou) {
+      ou[e] = R(cs * ux);
+      ou[p.ncell + e] = R(cs * uy);
+      if (D == 3) ou[2 * p.ncell + e] = R(cs * uz);
+    }
+    if (oth) oth[e] = R(theta);
+    const bool finite = isfinite(rho) && isfinite(U) && isfinite(theta);
+    if (!finite) {
+      acc[8] += 1.0;
+      continue;
+    }
+    acc[0] += rho;
+    acc[1] += rho * cs * ux;
+    acc[2] += rho * cs * uy;
+    acc[3] += rho * cs * uz;
+    acc[4] += 0.5 * cs * cs * U;
+    acc[5] += 0.5 * (Ef + G);
+    acc[6] = fmin(acc[6], rho);
+    acc[7] = fmin(acc[7], theta);
+  }
+  // block reduction (deterministic order)
+  __shared__ double red[NPART][256];
+#pragma unroll
+  for (int k = 0; k < NPART; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < NPART; ++k) {
+        if (k == 6 || k == 7) red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+        else red[k][threadIdx.x] += red[k][threadIdx.x + s];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < NPART) p.partial[int64_t(blockIdx.x) * NPART + threadIdx.x] = red[threadIdx.x][0];
+}
+
+// Final reduction of the block partials (one block).
+static __global__ __launch_bounds__(256) void reduce_partials_kernel(const double* partial, int nblocks, double* out) {
+  __shared__ double red[NPART][256];
+  double acc[NPART] = {0, 0, 0, 0, 0, 0, 1e300, 1e300, 0};
+  for (int b = threadIdx.x; b < nblocks; b += 256) {
+#pragma unroll
+    for (int k = 0; k < NPART; ++k) {
+      const double v = partial[int64_t(b) * NPART + k];
+      if (k == 6 || k == 7) acc[k] = fmin(acc[k], v);
+      else acc[k] += v;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NPART; ++k) red[k][threadIdx.x] = acc[k];
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+#pragma unroll
+      for (int k = 0; k < NPART; ++k) {
+        if (k == 6 || k == 7) red[k][threadIdx.x] = fmin(red[k][threadIdx.x], red[k][threadIdx.x + s]);
+        else red[k][threadIdx.x] += red[k][threadIdx.x + s];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < NPART) out[threadIdx.x] = red[threadIdx.x][0];
+}
+
+// lam_k = dK/df_k, K = (1/ncell) sum |u|^2/2, u = cs j~/rho:
+// lam_k = scale * cs^2 * u~ . (xh_k - u~) / rho
+template <int SET, int ST>
+__global__ __launch_bounds__(256) void ke_adjoint_kernel(CellParams p) {
+  using S = Set<SET>;
+  using TR = StoreT<ST>;
+  using R = typename TR::real;
+  using E = typename TR::elem;
+  constexpr int D = S::D, Q = S::Q;
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= p.ncell) return;
+  const E* f = static_cast<const E*>(p.f);
+  R* lam = static_cast<R*>(p.out_f);
+  R rho = R(0), jx = R(0), jy = R(0), jz = R(0);
+  static_for<Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    const R v = TR::ld(f + int64_t(q) * p.ncell + e);
+    rho += v;
+    jx = fma(R(S::xh(q, 0)), v, jx);
+    jy = fma(R(S::xh(q, 1)), v, jy);
+    jz = fma(R(S::xh(q, 2)), v, jz);
+  });
+  const R ux = jx / rho, uy = jy / rho, uz = (D == 3) ? jz / rho : R(0);
+  const R c = R(p.scale * p.cs * p.cs) / rho;
+  const R uu = ux * ux + uy * uy + uz * uz;
+  static_for<Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    const R a = R(S::xh(q, 0)) * ux + R(S::xh(q, 1)) * uy + R(S::xh(q, 2)) * uz;
+    lam[int64_t(q) * p.ncell + e] = c * (a - uu);
+  });
+}
+
+// grad_u = sum_k lam_k d f^eq_k / d u, with d f^eq/d u = (w rho / cs)(P_a xh + 2 P_U u~)
+template <int SET, int N, int ST>
+__global__ __launch_bounds__(256) void init_adjoint_kernel(CellParams p) {
+  using S = Set<SET>;
+  using TR = StoreT<ST>;
+  using R = typename TR::real;
+  constexpr int D = S::D, Q = S::Q;
+  const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (e >= p.ncell) return;
+  const R* rho_p = static_cast<const R*>(p.rho);
+  const R* u_p = static_cast<const R*>(p.u);
+  const R* lam = static_cast<const R*>(p.lam);
+  R* gu = static_cast<R*>(p.out_u);
+  const R inv_cs = R(1.0 / p.cs);
+  const R ux = u_p[e] * inv_cs, uy = u_p[p.ncell + e] * inv_cs;
+  const R uz = (D == 3) ? u_p[2 * p.ncell + e] * inv_cs : R(0);
+  const R U = ux * ux + uy * uy + uz * uz;
+  R gx = R(0), gy = R(0), gz = R(0);
+  static_for<Q>([&](auto qc) {
+    constexpr int q = decltype(qc)::value;
+    const R a = R(S::xh(q, 0)) * ux + R(S::xh(q, 1)) * uy + R(S::xh(q, 2)) * uz;
+    R Pq, Pa, PU;
+    peq_derivs<N, R>(a, U, Pq, Pa, PU);
+    const R lw = lam[int64_t(q) * p.ncell + e] * R(S::w(q));
+    gx = fma(lw, Pa * R(S::xh(q, 0)) + R(2) * PU * ux, gx);
+    gy = fma(lw, Pa * R(S::xh(q, 1)) + R(2) * PU * uy, gy);
+    gz = fma(lw, Pa * R(S::xh(q, 2)) + R(2) * PU * uz, gz);
+  });
+  const R c = rho_p[e] * inv_cs;
+  gu[e] = c * gx;
+  gu[p.ncell + e] = c * gy;
+  if (D == 3) gu[2 * p.ncell + e] = c * gz;
+}
+
+}  // namespace lbm

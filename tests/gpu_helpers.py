@@ -1,0 +1,48 @@
+"""Shared helpers of the GPU tests: build the GPU lattice and the oracle
+configuration of one problem from the same parameters, and compare states."""
+import numpy as np
+import torch
+
+from paper_2101_03982_amd import Lattice
+
+BC = {0: "periodic", 1: "extrapolate"}
+
+
+def pair(orc, set_, grid, tau, order=2, n=4, storage="f64", dx=1.0, dt=1.0, cs=0.0, compressible=False,
+         gamma=1.4, bc=(0, 0, 0), energy_f64=False):
+    """(GPU lattice, oracle config) of the same problem."""
+    lat = Lattice(set_, grid, tau, order, stencil=n, storage=storage, dx=dx, dt=dt, cs=cs,
+                  compressible=compressible, gamma=gamma, boundary=tuple(BC[b] for b in bc), energy_f64=energy_f64,
+                  device="cuda:0")
+    cfg = orc.Config(set_, tuple(grid) + (1,) * (3 - len(grid)), tau=tau, order=order, stencil=n, dx=dx, dt=dt,
+                     cs=cs, compressible=compressible, gamma=gamma, bc=bc)
+    return lat, cfg
+
+
+def to_dev(a, dtype):
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", dtype)
+
+
+def init_both(lat, orc, cfg, rho, u, theta=None):
+    lat.init_equilibrium(to_dev(rho, lat.dtype), to_dev(u, lat.dtype), to_dev(theta, lat.dtype))
+    return orc.init(cfg, rho, u, theta)
+
+
+def gpu_populations(lat, state=None):
+    """The state as float64 numpy populations (deviation storage adds back the
+    reference values w_i and (2 C_v - D) w_i)."""
+    f = (lat.state() if state is None else state).to(torch.float64).cpu().numpy()
+    if lat.storage in ("bf16", "f16"):
+        t = lat.table()
+        w = np.array(t["w"])
+        ref = [w]
+        if lat.A == 2:
+            Cv = 1.0 / (lat.gamma - 1.0)
+            ref.append((2 * Cv - lat.D) * w)
+        f = f + np.concatenate(ref).reshape((-1,) + (1,) * 3)
+    return f
+
+
+def rel_err(a, b):
+    """max |a - b| / max |b|."""
+    return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))

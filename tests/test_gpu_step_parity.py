@@ -1,0 +1,84 @@
+"""GPU time step vs the FP64 CPU oracle, element by element.
+
+Grids span several 64-wide x tiles, several y/z tiles and a ragged tail on
+every axis; populations start at the equilibrium of seeded random fields with
+the velocity amplitude of the paper's weakly compressible runs.  The bar:
+FP64 storage within 1e-12 of the oracle relative to the largest population,
+FP32 within 3e-6 (a few FP32 roundings per tap and per collision term)."""
+import numpy as np
+import pytest
+
+import lbm_inputs as W
+from gpu_helpers import init_both, gpu_populations, pair, rel_err
+
+pytestmark = pytest.mark.gpu
+
+SETS = ["D2Q9", "D2Q19", "D2Q25", "D3Q13", "D3Q21", "D3Q27", "D3V27", "D3Q45"]
+TOL = {"f64": 1e-12, "f32": 3e-6}
+
+
+def grid_for(D):
+    return (70, 13, 7) if D == 3 else (70, 21, 1)
+
+
+def problem(orc, name, storage, n, order=2, dt_cells=0.45, steps=3, seed=0, grid=None):
+    D = W.DIM[name]
+    grid = grid or grid_for(D)
+    cs = 0.6
+    # shifts of up to dt_cells cells along the fastest component
+    dt = dt_cells / (W.MAX_COMPONENT_OVER_CS[name] * cs)
+    lat, cfg = pair(orc, name, grid, tau=0.57, order=order, n=n, storage=storage, dx=1.0, dt=dt, cs=cs)
+    rho, u, _ = W.random_fields(D, cfg.shape, seed, u_amp=0.1 * cs, rho_amp=0.02)
+    f0 = init_both(lat, orc, cfg, rho, u)
+    lat.step(steps)
+    ref = orc.run(cfg, f0, steps)
+    return gpu_populations(lat), ref
+
+
+@pytest.mark.parametrize("name", SETS)
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_step_parity_all_sets(orc, name, storage):
+    got, ref = problem(orc, name, storage, n=4)
+    assert rel_err(got, ref) <= TOL[storage], rel_err(got, ref)
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D2Q19", "D3Q13", "D3Q27", "D3Q45"])
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+def test_step_parity_stencil_lengths(orc, name, n):
+    got, ref = problem(orc, name, "f64", n=n)
+    assert rel_err(got, ref) <= 1e-12, rel_err(got, ref)
+
+
+@pytest.mark.parametrize("name,order", [("D3V27", 3), ("D2Q25", 3), ("D2Q19", 4), ("D3Q45", 3), ("D3Q45", 4)])
+def test_step_parity_higher_orders(orc, name, order):
+    got, ref = problem(orc, name, "f64", n=4, order=order)
+    assert rel_err(got, ref) <= 1e-12, rel_err(got, ref)
+
+
+@pytest.mark.parametrize("name", ["D2Q19", "D3Q21", "D3Q45"])
+def test_large_courant_number(orc, name):
+    """Shifts of several cells (the paper's large time steps, Sec. 4.3)."""
+    grid = (70, 13, 12) if W.DIM[name] == 3 else (70, 21, 1)
+    got, ref = problem(orc, name, "f64", n=4, dt_cells=3.7, steps=2, grid=grid)
+    assert rel_err(got, ref) <= 1e-12, rel_err(got, ref)
+
+
+def test_zero_steps_is_a_no_op(orc):
+    lat, cfg = pair(orc, "D3Q13", (66, 5, 5), tau=0.6, n=4, storage="f64", dt=0.2)
+    rho, u, _ = W.random_fields(3, cfg.shape, 1, 0.05)
+    init_both(lat, orc, cfg, rho, u)
+    before = lat.state().clone()
+    lat.step(0)
+    assert np.array_equal(before.cpu().numpy(), lat.state().cpu().numpy())
+
+
+def test_minimal_grid(orc):
+    """The smallest periodic grid the stencil allows, one tile, all tails."""
+    got, ref = None, None
+    name = "D3Q27"
+    lat, cfg = pair(orc, name, (6, 6, 6), tau=0.7, n=4, storage="f64", dt=0.3, cs=1.0)
+    rho, u, _ = W.random_fields(3, cfg.shape, 4, 0.1)
+    f0 = init_both(lat, orc, cfg, rho, u)
+    lat.step(2)
+    got, ref = gpu_populations(lat), orc.run(cfg, f0, 2)
+    assert rel_err(got, ref) <= 1e-12

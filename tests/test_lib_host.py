@@ -1,0 +1,156 @@
+"""Host-side checks of liblbm.so that need no GPU: the library loads and
+exports every entry point declared in include/lbm.h; its velocity-set tables
+match the oracle's (same order and values); its host stencil generator
+matches the oracle's streaming weights; argument validation of lbm_create."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbm.h")
+SETS = ["D2Q9", "D2Q19", "D2Q25", "D3Q13", "D3Q21", "D3Q27", "D3V27", "D3Q45"]
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2101_03982_amd import _lib
+
+    return _lib
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(L):
+    names = declared_functions()
+    assert len(names) >= 20
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding declares each of them
+    assert set(names) <= set(L._SIGS), set(names) - set(L._SIGS)
+
+
+def test_abi_and_strerror(L):
+    lib = L.lib()
+    assert lib.lbm_abi_version() == 1
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.lbm_strerror(code)
+    assert lib.lbm_strerror(-99) == b"unknown status"
+
+
+@pytest.mark.parametrize("name", SETS)
+def test_tables_agree_with_oracle(orc, name):
+    from paper_2101_03982_amd import set_table
+
+    lt = set_table(name)
+    ot = orc.table(name)
+    assert (lt["Q"], lt["D"], lt["degree"]) == (ot["Q"], ot["D"], ot["degree"])
+    assert lt["cs"] == ot["cs"]
+    # D2Q25 weights: closed form (7 +- 2 sqrt 10)/60 here, 5!/(25 He_4^2) in the oracle
+    assert np.allclose(lt["w"], ot["w"], rtol=5e-15, atol=0)
+    assert np.allclose(lt["xi"], ot["xi"], rtol=4e-16, atol=1e-300)
+
+
+@pytest.mark.parametrize("name,dt,n", [("D2Q19", 0.37, 3), ("D3Q21", 0.41, 4), ("D3Q45", 0.23, 5),
+                                       ("D2Q9", 0.5, 3), ("D3V27", 0.9, 2), ("D3Q13", 1.3, 4)])
+def test_stencil_matches_oracle_weights(orc, name, dt, n):
+    """Stream a delta with the oracle; the response of population i is the
+    tensor product of the library's 1D weights at its offsets."""
+    from paper_2101_03982_amd import stencil
+
+    t = orc.table(name)
+    D = t["D"]
+    N = 14
+    grid = (N, N, N) if D == 3 else (N, N, 1)
+    cfg = orc.Config(name, grid, tau=1.0, stencil=n, dx=1.0, dt=dt)
+    off, w = stencil(name, dt, 1.0, 0.0, n)
+    f = np.zeros(cfg.pop_shape())
+    c = N // 2
+    if D == 3:
+        f[:, c, c, c] = 1.0
+    else:
+        f[:, 0, c, c] = 1.0
+    out = orc.stream(cfg, f)
+    for i in range(t["Q"]):
+        exp = np.zeros(cfg.shape)
+        taps = [range(n) if t["xi"][i][a] != 0 else range(1) for a in range(D)]
+        import itertools
+
+        for ks in itertools.product(*taps):
+            # node = j + off + k holds the delta => j = c - off - k
+            j = [c - off[i, a] - ks[a] for a in range(D)]
+            val = np.prod([w[i, a, ks[a]] for a in range(D)])
+            if D == 3:
+                exp[j[2] % N, j[1] % N, j[0] % N] += val
+            else:
+                exp[0, j[1] % N, j[0] % N] += val
+        assert np.allclose(out[i], exp, rtol=0, atol=1e-14), (name, i)
+
+
+def _create(L, set_id, grid, tau=0.8, order=2, **opt):
+    lib = L.lib()
+    o = L.Options()
+    lib.lbm_default_options(ctypes.byref(o))
+    for k, v in opt.items():
+        if k == "boundary":
+            for a in range(3):
+                o.boundary[a] = v[a]
+        else:
+            setattr(o, k, v)
+    ctx = ctypes.c_void_p()
+    g = (ctypes.c_int64 * 3)(*grid)
+    rc = lib.lbm_create(ctypes.byref(ctx), set_id, g, tau, order, ctypes.byref(o))
+    if rc == 0:
+        lib.lbm_destroy(ctx)
+    return rc, ctx.value
+
+
+@pytest.mark.parametrize("args,code", [
+    ((99, (8, 8, 8)), -1),                                  # unknown set
+    ((5, (0, 8, 8)), -1),                                   # empty grid
+    ((0, (8, 8, 2)), -1),                                   # 2D set with nz != 1
+    ((5, (8, 8, 8), 0.5), -1),                              # tau must exceed 1/2
+    ((5, (8, 8, 8), 0.8, 3), -4),                           # N = 3 needs degree >= 6
+    ((7, (8, 8, 8), 0.8, 5), -1),                           # order out of range
+    ((5, (8, 8, 8), 0.8, 2, {"stencil": 6}), -1),           # stencil too long
+    ((5, (8, 8, 8), 0.8, 2, {"stencil": 0}), -1),
+    ((0, (8, 8, 1), 0.8, 2, {"storage": 2}), -4),           # 16-bit storage only for 3D sets
+    ((5, (8, 8, 8), 0.8, 2, {"dt": 0.0}), -1),
+    ((5, (8, 8, 8), 0.8, 2, {"dx": -1.0}), -1),
+    ((5, (4, 8, 8), 0.8, 2, {"dt": 3.0, "cs": 1.0}), -1),    # stencil reach exceeds the grid
+    ((3, (8, 8, 8), 0.8, 2, {"compressible": 1}), -4),      # compressible needs N = 4
+    ((7, (8, 8, 8), 0.8, 4, {"compressible": 1, "gamma": 1.0}), -1),
+    ((5, (8, 8, 8), 0.8, 2, {"boundary": (0, 2, 0)}), -1),
+])
+def test_create_rejects(L, args, code):
+    set_id, grid = args[0], args[1]
+    tau = args[2] if len(args) > 2 else 0.8
+    order = args[3] if len(args) > 3 else 2
+    opt = args[4] if len(args) > 4 else {}
+    rc, ctx = _create(L, set_id, grid, tau, order, **opt)
+    assert rc == code, L.lib().lbm_last_error()
+    assert ctx is None
+
+
+def test_null_arguments(L):
+    lib = L.lib()
+    assert lib.lbm_create(None, 0, None, 1.0, 2, None) == -1
+    assert lib.lbm_step(None, 1) == -1
+    assert lib.lbm_destroy(None) == 0
+    assert lib.lbm_state_bytes(None) == 0
+
+
+def test_lattice_refuses_cpu_device():
+    import torch
+
+    from paper_2101_03982_amd import Lattice
+
+    with pytest.raises(ValueError):
+        Lattice("D2Q9", (8, 8), tau=0.8, device=torch.device("cpu"))
