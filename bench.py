@@ -1,0 +1,345 @@
+"""Throughput of the semi-Lagrangian lattice Boltzmann step on one MI355X.
+
+Workload: the weakly compressible 3D Taylor-Green vortex on a 128^3 periodic
+grid in FP32 with the four velocity sets of Sec. 4.2 (D3Q13, D3Q21, D3V27,
+D3Q27), tricubic Lagrange streaming (n = 4) at Courant number 0.5, Ma 0.1,
+Re 1600, N = 2 (N = 3 for D3V27); kinetic energy logged every 50 steps.  One
+bench step advances all four lattices by one time step.  Inputs are the
+analytic initial fields, resident in HBM before timing starts.
+
+Prints one JSON line: MLUPS of the whole workload, per-set MLUPS and fraction
+of HBM peak, the roofline of the dominant kernel (HIP-event timing of single
+launches on the lattice's stream), and the FP64 CPU oracle timed on a bounded
+sample of the same workload on this host's cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+SETS = ("D3Q13", "D3Q21", "D3V27", "D3Q27")
+KERNEL_SRC = os.path.join(ROOT, "paper_2101_03982_amd", "csrc", "lbm_kernels.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=128, help="grid points per axis")
+    ap.add_argument("--log-every", type=int, default=50)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the FP64-error, adjoint-cost and reduced-precision measurements")
+    ap.add_argument("--precision-n", type=int, default=256)
+    ap.add_argument("--precision-steps", type=int, default=1000)
+    ap.add_argument("--sets", default=",".join(SETS))
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
+    return ap.parse_args()
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def traffic_for(set_name, n):
+    """HBM bytes per launch from the committed PMC counters, if they were taken
+    with the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha():
+        return None
+    e = t.get("kernels", {}).get("%s_%d" % (set_name, n))
+    return None if e is None else e.get("bytes_per_launch")
+
+
+def cpu_baseline(sets, n):
+    """The FP64 oracle, one time step of every set at the full grid size."""
+    import numpy as np  # noqa: F401
+
+    import lbm_inputs as W
+    from oracle import oracle as O
+
+    O.build()
+    t_total = 0.0
+    cells = 0
+    for s in sets:
+        wl = W.tgv3d_workload(s, n=n)
+        cfg = O.Config(wl.set, wl.grid, tau=wl.tau, order=wl.order, stencil=wl.stencil, dx=wl.dx, dt=wl.dt,
+                       cs=wl.cs)
+        rho, u, _ = W.tgv3d_fields(wl)
+        f = O.init(cfg, rho, u)
+        t0 = time.perf_counter()
+        O.step(cfg, f)
+        t_total += time.perf_counter() - t0
+        cells += wl.ncell
+        del f
+    return {"value": cells / t_total / 1e6, "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+            "sample": "one FP64 time step of each of %s on the %d^3 grid (%.1f s)" % ("/".join(sets), n, t_total)}
+
+
+def fp64_error(sets, n, steps, ke32):
+    """KE of an FP64 run of the same workload after the same number of steps,
+    and the FP32 run's relative deviation from it."""
+    import torch
+
+    import lbm_inputs as W
+    from paper_2101_03982_amd import Lattice
+
+    out = {}
+    for s in sets:
+        wl = W.tgv3d_workload(s, n=n)
+        lat = Lattice(s, wl.grid, wl.tau, wl.order, stencil=wl.stencil, storage="f64", dx=wl.dx, dt=wl.dt,
+                      cs=wl.cs, device="cuda:0")
+        rho, u, _ = W.tgv3d_fields(wl)
+        lat.init_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+        lat.step(steps)
+        ke64 = lat.moments(fields=False)[3].ke
+        out[s] = {"ke_fp64": ke64, "ke_fp32": ke32[s], "ke_rel_err": abs(ke32[s] / ke64 - 1)}
+        lat.close()
+        del lat
+    return out
+
+
+def adjoint_cost(n=64, steps=200, every=20):
+    """Differentiation workload: D3Q27, FP32, loss = final kinetic energy,
+    gradient w.r.t. the initial velocity with checkpoints every `every` steps.
+    Times the forward (with checkpointing) and the backward (recompute +
+    adjoint kernels) with CUDA events."""
+    import torch
+
+    import lbm_inputs as W
+    from paper_2101_03982_amd import Lattice, kinetic_energy_after
+
+    wl = W.adjoint_workload(n=n, steps=steps, storage="f32")
+    lat = Lattice(wl.set, wl.grid, wl.tau, wl.order, stencil=wl.stencil, storage="f32", dx=wl.dx, dt=wl.dt,
+                  cs=wl.cs, device="cuda:0")
+    rho_np, u_np, _ = W.tgv3d_fields(wl, sigma=1e-3, seed=1)
+    rho = torch.from_numpy(rho_np).to("cuda:0", torch.float32)
+    times = []
+    for rep in range(3):
+        u0 = torch.from_numpy(u_np).to("cuda:0", torch.float32).requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        K = kinetic_energy_after(u0, rho, lat, steps, every=every)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        K.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        times.append((t1 - t0, t2 - t1))
+    fwd, bwd = min(times, key=lambda t: t[0] + t[1])
+    # plain forward without checkpoints, for reference
+    lat.init_equilibrium(rho, torch.from_numpy(u_np).to("cuda:0", torch.float32))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat.step(steps)
+    torch.cuda.synchronize()
+    plain = time.perf_counter() - t0
+    return {"workload": "D3Q27 %d^3 FP32, %d steps, checkpoints every %d, loss = final kinetic energy" % (
+        n, steps, every), "forward_s": fwd, "backward_s": bwd, "plain_forward_s": plain,
+        "adjoint_over_forward": bwd / fwd, "adjoint_over_plain_forward": bwd / plain}
+
+
+def precision_form(n=256, steps=1000, machs=(0.5, 1.0)):
+    """Compressible TGV with D3Q45 (N = 4, n = 4): time per step and error
+    after `steps` steps of the BF16/FP16 deviation storage and of FP32 against
+    the FP64 run on the same GPU."""
+    import numpy as np
+    import torch
+
+    import lbm_inputs as W
+    from paper_2101_03982_amd import Lattice
+
+    res = {}
+    for Ma in machs:
+        wl = W.ctgv_workload(n=n, Ma=Ma)
+        rho_np, u_np, th_np = W.ctgv_fields(wl)
+        ref = None
+        entry = {}
+        for st in ("f64", "f32", "bf16", "f16"):
+            lat = Lattice("D3Q45", wl.grid, wl.tau, 4, stencil=wl.stencil, storage=st, dx=wl.dx, dt=wl.dt,
+                          cs=wl.cs, compressible=True, gamma=wl.gamma, energy_f64=(st in ("bf16", "f16")),
+                          device="cuda:0")
+            dt_ = lat.dtype
+            lat.init_equilibrium(torch.from_numpy(rho_np).to("cuda:0", dt_), torch.from_numpy(u_np).to("cuda:0", dt_),
+                                 torch.from_numpy(th_np).to("cuda:0", dt_))
+            lat.step(5)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            lat.step(steps - 5)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / (steps - 5)
+            try:
+                r, u, th, d = lat.moments()
+                fields = (r.double(), u.double(), th.double())
+                ok = True
+            except Exception as exc:  # noqa: BLE001 - reported in the JSON
+                fields, d, ok = None, None, str(exc)
+            bpc = 2 * 90 * {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[st]
+            e = {"ms_per_step": ms, "mlups": wl.ncell / (ms * 1e-3) / 1e6,
+                 "achieved_GBs": bpc * wl.ncell / (ms * 1e-3) / 1e9, "ok": ok}
+            if ok is True:
+                e["ke"] = d.ke
+                if st == "f64":
+                    ref = fields
+                elif ref is not None:
+                    def rl2(a, b):
+                        return float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+                    e["rel_l2_rho"] = rl2(fields[0], ref[0])
+                    e["rel_l2_u"] = rl2(fields[1], ref[1])
+                    e["rel_l2_theta"] = rl2(fields[2], ref[2])
+                    e["ke_rel_err"] = abs(d.ke / entry["f64"]["ke"] - 1)
+            entry[st] = e
+            lat.close()
+            del lat
+            torch.cuda.empty_cache()
+        if "f32" in entry and "bf16" in entry:
+            entry["speedup_bf16_over_f32"] = entry["f32"]["ms_per_step"] / entry["bf16"]["ms_per_step"]
+            entry["speedup_f16_over_f32"] = entry["f32"]["ms_per_step"] / entry["f16"]["ms_per_step"]
+        res["Ma%.1f" % Ma] = entry
+    res["workload"] = "compressible TGV (CTIC) D3Q45 f+g, N = 4, n = 4, %d^3, Re 1600, %d steps" % (n, steps)
+    return res
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path (got --gpus %d)" % a.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import lbm_inputs as W
+    from paper_2101_03982_amd import Lattice
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    sets = tuple(a.sets.split(","))
+    if a.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    lats = []
+    for s in sets:
+        wl = W.tgv3d_workload(s, n=a.n)
+        lat = Lattice(s, wl.grid, wl.tau, wl.order, stencil=wl.stencil, storage="f32", dx=wl.dx, dt=wl.dt,
+                      cs=wl.cs, device=dev)
+        rho, u, _ = W.tgv3d_fields(wl)
+        lat.init_equilibrium(torch.from_numpy(rho).to(dev, torch.float32),
+                             torch.from_numpy(u).to(dev, torch.float32))
+        lats.append((s, wl, lat))
+    torch.cuda.synchronize()
+
+    ke_log = {s: [] for s in sets}
+
+    def one_step(k):
+        for s, _, lat in lats:
+            lat.step(1)
+            if a.log_every and (k + 1) % a.log_every == 0:
+                _, _, _, d = lat.moments(fields=False)
+                ke_log[s].append(d.ke)
+
+    for k in range(a.warmup):
+        one_step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        one_step(k)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    # per-launch kernel time with HIP events on the lattices' stream
+    stream = torch.cuda.current_stream(dev)
+    per_set = {}
+    reps = 50
+    for s, wl, lat in lats:
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in evs:
+            e0.record(stream)
+            lat.step(1)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        ms = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+        avg_ms = sum(ms) / len(ms)
+        bpc = 2 * lat.Q * 4  # one FP32 read and one write of every population per cell update
+        gbs = bpc * wl.ncell / (avg_ms * 1e-3) / 1e9
+        per_set[s] = {"kernel_ms": avg_ms, "kernel_ms_median": ms[len(ms) // 2],
+                      "mlups": wl.ncell / (avg_ms * 1e-3) / 1e6, "bytes_per_cell": bpc,
+                      "achieved_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                      "ke_log": ke_log[s][-3:]}
+    dominant = max(per_set, key=lambda s: per_set[s]["kernel_ms"])
+    dom = per_set[dominant]
+    ncells = sum(wl.ncell for _, wl, _ in lats)
+    value = ncells * a.steps / elapsed / 1e6
+    tr = traffic_for(dominant, a.n)
+    roof = {"bound": "hbm", "kernel": "sl_kernel %s n=4 N=%d FP32 %d^3" % (
+        dominant, 3 if dominant == "D3V27" else 2, a.n),
+        "achieved": round(dom["achieved_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": tr,
+        "algorithmic_bytes_per_launch": dom["bytes_per_cell"] * a.n ** 3}
+    out = {
+        "metric": "MLUPS & %HBM peak per velocity set; adjoint/forward time; err vs FP64",
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "3D Taylor-Green vortex %d^3 periodic, %s, tricubic semi-Lagrangian streaming, "
+                               "Courant 0.5, Ma 0.1, Re 1600, FP32, KE logged every %d steps" % (
+                                   a.n, "/".join(sets), a.log_every),
+                   "grid": [a.n] * 3, "sets": list(sets), "stencil": 4},
+        "per_set": {s: {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+                    for s, d in per_set.items()},
+        "roofline": roof,
+    }
+    if not a.no_extras:
+        ke32 = {}
+        for s, wl, lat in lats:
+            ke32[s] = lat.moments(fields=False)[3].ke
+        steps_done = a.warmup + a.steps + reps
+        for s, wl, lat in lats:
+            lat.close()
+        del lats
+        torch.cuda.empty_cache()
+        out["err_vs_fp64"] = fp64_error(sets, a.n, steps_done, ke32)
+        out["adjoint"] = adjoint_cost()
+        torch.cuda.empty_cache()
+        out["precision"] = precision_form(a.precision_n, a.precision_steps)
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(sets, a.n)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

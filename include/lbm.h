@@ -28,10 +28,11 @@
  *    message of the most recent failure on the calling thread.
  *  - Population buffers are caller-owned device memory in the layout
  *    [A*Q][nz][ny][nx], x fastest, f populations then g populations (A = 2
- *    only in the compressible model), element type by storage:
- *    LBM_F64 double, LBM_F32 float, LBM_BF16DEV bfloat16 and LBM_F16DEV
+ *    only in the compressible model), element type by storage: LBM_F64
+ *    double holding f_i; LBM_F32 float, LBM_BF16DEV bfloat16 and LBM_F16DEV
  *    IEEE half holding the deviation f_i - r_i from the reference
- *    r_i = w_i (f) or (2 C_v - D) w_i (g).  lbm_state_bytes() gives the size.
+ *    r_i = w_i (f) or (2 C_v - D) w_i (g), which keeps the storage precision
+ *    on the part of f_i that varies.  lbm_state_bytes() gives the size.
  *  - Macroscopic fields (rho, u, theta) are device arrays of the compute type:
  *    double for LBM_F64 storage, float otherwise; u is [D][nz][ny][nx] in the
  *    physical units of dx and dt.
@@ -71,7 +72,7 @@ typedef enum lbm_set {
 
 typedef enum lbm_storage {
   LBM_F64 = 0,      /* double populations, double arithmetic */
-  LBM_F32 = 1,      /* float populations, float arithmetic */
+  LBM_F32 = 1,      /* float deviations f - r, float arithmetic */
   LBM_BF16DEV = 2,  /* bfloat16 deviations f - r, float arithmetic */
   LBM_F16DEV = 3    /* IEEE half deviations f - r, float arithmetic */
 } lbm_storage;

@@ -134,6 +134,21 @@ int set_device(const lbm_ctx* c) {
   return LBM_OK;
 }
 
+// 1 / sum_i w_i xh_ia^2 evaluated with the weights and abscissae rounded to
+// the kernels' compute type (exactly 1 for exact constants).
+void momentum_norm(const lbm_ctx* c, double* cm) {
+  const SetTable t = set_table(c->set);
+  for (int a = 0; a < 3; ++a) {
+    double s = 0.0;
+    for (int i = 0; i < t.Q; ++i) {
+      const double w = compute_is_f64(c) ? t.w[i] : double(float(t.w[i]));
+      const double x = compute_is_f64(c) ? t.xh[i][a] : double(float(t.xh[i][a]));
+      s += w * x * x;
+    }
+    cm[a] = (a < c->D && s > 0) ? 1.0 / s : 1.0;
+  }
+}
+
 KParams base_params(const lbm_ctx* c) {
   KParams p{};
   p.off = c->d_off;
@@ -154,6 +169,7 @@ KParams base_params(const lbm_ctx* c) {
   for (int a = 0; a < 3; ++a) p.swx[a] = c->swx[a];
   p.swX = c->swX;
   p.e64 = c->e64 ? 1.0 : 0.0;
+  momentum_norm(c, p.cmom);
   return p;
 }
 
@@ -168,6 +184,7 @@ CellParams base_cell(const lbm_ctx* c) {
   p.swX = c->swX;
   for (int a = 0; a < 3; ++a) p.swx[a] = c->swx[a];
   p.scale = 1.0 / double(c->ncell);
+  momentum_norm(c, p.cmom);
   return p;
 }
 

@@ -22,18 +22,25 @@ struct Kernels {
 constexpr int MOMENT_BLOCKS = 1024;
 
 // Which combinations are compiled.  Every set gets the forward step for each
-// stencil length 2..5 (1: on-lattice copy, D2Q9 and D3Q27 only) and each
-// Hermite order with 2N <= degree; the compressible model (two arrays) with
-// N = 4; 16-bit deviation storage on the 3D sets; the adjoint modes with
-// FP64/FP32 storage in the weakly compressible model.
+// stencil length 2..5 (1: the on-lattice copy, D2Q9 and D3Q27 only).
+// Hermite orders: N = 2 everywhere; N = 3 for the degree-7 set (D3V27); N = 4
+// for the degree-9 sets.  The compressible model (two arrays) uses N = 4.
+// 16-bit deviation storage: the 3D sets at their workload order (N = 2,
+// N = 3 for D3V27) and D3Q45 compressible.  Adjoint modes: FP64/FP32, weakly
+// compressible, N = 2.
 template <int SET, int NS, int N, int A, int ST>
 constexpr bool combo_built() {
   constexpr int D = Set<SET>::D;
   constexpr int deg = Set<SET>::degree;
   if (2 * N > deg) return false;
+  if (N == 3 && deg != 7) return false;
   if (A == 2 && N != 4) return false;
   if (NS == 1 && !(SET == D2Q9 || SET == D3Q27)) return false;
-  if ((ST == ST_BF16 || ST == ST_F16) && D != 3) return false;
+  if (ST == ST_BF16 || ST == ST_F16) {
+    if (D != 3) return false;
+    if (SET == D3Q45) return A == 2;
+    return A == 1 && N == (deg == 7 ? 3 : 2);
+  }
   return true;
 }
 
@@ -41,7 +48,7 @@ template <int SET, int NS, int N, int A, int ST, int MODE>
 constexpr bool mode_built() {
   if (!combo_built<SET, NS, N, A, ST>()) return false;
   if (MODE == MODE_STEP) return true;
-  return A == 1 && N <= 3 && (ST == ST_F64 || ST == ST_F32);
+  return A == 1 && N == 2 && (ST == ST_F64 || ST == ST_F32);
 }
 
 // Which (set, storage, stencil length) parts exist as compiled units.

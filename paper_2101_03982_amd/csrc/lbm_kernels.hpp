@@ -52,24 +52,33 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return uint16_t(u >> 16);
 }
 
+// dev: the kernels compute on deviations d = f - r from the reference values
+//      r_i = w_i (f) and (2 C_v - D) w_i (g), which keeps rounding relative to
+//      the small deviations instead of the populations;
+// stores_dev: the buffer itself holds deviations (16-bit storage);
+// kahan: moment sums with compensated summation.
 template <int S> struct StoreT;
 template <> struct StoreT<ST_F64> {
-  using elem = double; using real = double; static constexpr bool dev = false;
+  using elem = double; using real = double;
+  static constexpr bool dev = false, stores_dev = false, kahan = false;
   static __device__ __forceinline__ real ld(const elem* p) { return *p; }
   static __device__ __forceinline__ void st(elem* p, real v) { *p = v; }
 };
 template <> struct StoreT<ST_F32> {
-  using elem = float; using real = float; static constexpr bool dev = false;
+  using elem = float; using real = float;
+  static constexpr bool dev = true, stores_dev = true, kahan = false;
   static __device__ __forceinline__ real ld(const elem* p) { return *p; }
   static __device__ __forceinline__ void st(elem* p, real v) { *p = v; }
 };
 template <> struct StoreT<ST_BF16> {
-  using elem = uint16_t; using real = float; static constexpr bool dev = true;
+  using elem = uint16_t; using real = float;
+  static constexpr bool dev = true, stores_dev = true, kahan = true;
   static __device__ __forceinline__ real ld(const elem* p) { return bf16_to_f32(*p); }
   static __device__ __forceinline__ void st(elem* p, real v) { *p = f32_to_bf16(v); }
 };
 template <> struct StoreT<ST_F16> {
-  using elem = _Float16; using real = float; static constexpr bool dev = true;
+  using elem = _Float16; using real = float;
+  static constexpr bool dev = true, stores_dev = true, kahan = true;
   static __device__ __forceinline__ real ld(const elem* p) { return float(*p); }
   static __device__ __forceinline__ void st(elem* p, real v) { *p = _Float16(v); }
 };
@@ -109,6 +118,8 @@ struct KParams {
   int n[3];            // nx, ny, nz
   int bc[3];           // 0 periodic, 1 extrapolate (clamp)
   int64_t pstride;     // cells per population
+  int tiles[3];        // tiles along x, y (3D) / outer (2D), z (3D)
+  int chunk;           // tiles per XCD: consecutive logical tiles share an L2
   double omega;        // 1 / tau (weakly compressible)
   double tau_m_half;   // tau_ref - 1/2 (compressible)
   double cv2mD;        // 2 C_v - D
@@ -117,6 +128,7 @@ struct KParams {
   double swx[3];       // sum_i w_i xh_i
   double swX;          // sum_i w_i |xh_i|^2
   double e64;          // nonzero: compressible energy moment summed in FP64
+  double cmom[3];      // 1 / sum_i w_i xh_ia^2 with the compute type's rounded constants
 };
 
 // Cells per thread along the register (outer) axis.
@@ -124,7 +136,7 @@ template <int D, int Q, int A, int RBYTES, int MODE>
 constexpr int cells_per_thread() {
   constexpr int vals = A * Q * (RBYTES / 4) * ((MODE == MODE_ADJ_STEP || MODE == MODE_ADJ_COLLIDE) ? 2 : 1);
   if (D == 2) return vals <= 40 ? 4 : (vals <= 80 ? 2 : 1);
-  return vals <= 30 ? 4 : (vals <= 60 ? 2 : 1);
+  return vals <= 30 ? 4 : (vals <= 90 ? 2 : 1);
 }
 
 // Node index on the grid: periodic wrap (valid for i in [-n, 2n)) or, on an
@@ -167,6 +179,16 @@ struct Geo {
   int lane, w, tid;
 };
 
+// The stencil tables are read-only for the whole launch: reading them through
+// the constant address space lets the compiler use scalar loads (one fetch
+// per wave, no vector-memory round trip before the data loads).
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)(p);
+}
+
 // Element at a 32-bit element offset from a per-population base pointer
 // (the host guarantees that one population spans less than 4 GiB), so that
 // loads use a scalar base and a 32-bit vector offset.
@@ -179,94 +201,93 @@ __device__ __forceinline__ E* at(E* base, int e) {
   return reinterpret_cast<E*>(reinterpret_cast<char*>(base) + uint32_t(e) * uint32_t(sizeof(E)));
 }
 
-// Interpolate population q (all A arrays) of `src` with stencil (off, wts)
-// into out[a][r], using the LDS buffers P and T of the current parity.
+// Shape of population q's work: which axes move (and so need n taps and a
+// halo), how many source columns phase A covers, and in how many rounds of
+// 256 threads.
 template <int SET, int NS, int A, int ST, int RO, int q>
-__device__ __forceinline__ void interp_pop(const Geo& g, const typename StoreT<ST>::elem* __restrict__ src,
-                                           int64_t pstride, const int* __restrict__ off,
-                                           const typename StoreT<ST>::real* __restrict__ wts,
-                                           typename StoreT<ST>::real* P, typename StoreT<ST>::real* T,
-                                           typename StoreT<ST>::real (&out)[A][RO]) {
+struct PopShape {
   using TL = Tile<SET, NS, A, ST, RO>;
   using S = typename TL::S;
+  static constexpr int D = S::D;
+  static constexpr bool mx = NS > 1 && S::moves(q, 0);
+  static constexpr bool mm = NS > 1 && D == 3 && S::moves(q, 1);
+  static constexpr bool mo = NS > 1 && S::moves(q, D - 1);
+  static constexpr bool direct = !mx && !mm;  // no LDS: each thread loads its own column
+  static constexpr int HX = mx ? NS - 1 : 0, HM = mm ? NS - 1 : 0, HO = mo ? NS - 1 : 0;
+  static constexpr int KX = mx ? NS : 1, KM = mm ? NS : 1, KO = mo ? NS : 1;
+  static constexpr int CX = TL::TX + HX;
+  static constexpr int CM = (D == 3) ? TL::NW + HM : TL::NW;
+  static constexpr int NCOL = CX * CM;
+  static constexpr int ROUNDS = direct ? 1 : (NCOL + 255) / 256;
+};
+
+// Everything population q needs after its loads were issued: the loaded
+// values (still in flight until first use), the stencil weights and where
+// each round's column lands in LDS.
+template <int SET, int NS, int A, int ST, int RO, int q>
+struct PopIn {
+  using PS = PopShape<SET, NS, A, ST, RO, q>;
+  using R = typename StoreT<ST>::real;
+  R v[PS::ROUNDS][A][RO + PS::HO];
+  R wx[PS::KX], wm[PS::KM], wo[PS::KO];
+  int slot[PS::ROUNDS];
+};
+
+// Issue the HBM loads of population q (all A arrays) of `src` with stencil
+// (off, wts).  With SUB every loaded value has ref[a] subtracted (exact for
+// values within a factor two of the reference), so the interpolation works
+// on deviations.
+template <int SET, int NS, int A, int ST, int RO, int q, bool SUB>
+__device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>::elem* __restrict__ src,
+                                         int64_t pstride, const int* __restrict__ off,
+                                         const typename StoreT<ST>::real* __restrict__ wts,
+                                         const typename StoreT<ST>::real (&ref)[A],
+                                         PopIn<SET, NS, A, ST, RO, q>& in) {
+  using PS = PopShape<SET, NS, A, ST, RO, q>;
+  using TL = typename PS::TL;
   using TR = StoreT<ST>;
   using R = typename TR::real;
   using E = typename TR::elem;
-  constexpr int D = S::D;
-  constexpr int Q = S::Q;
-  constexpr bool mx = NS > 1 && S::moves(q, 0);
-  constexpr bool mm = NS > 1 && D == 3 && S::moves(q, 1);
-  constexpr bool mo = NS > 1 && S::moves(q, D - 1);
-  constexpr int HX = mx ? NS - 1 : 0;
-  constexpr int HM = mm ? NS - 1 : 0;
-  constexpr int HO = mo ? NS - 1 : 0;
-  constexpr int KX = mx ? NS : 1, KM = mm ? NS : 1, KO = mo ? NS : 1;
+  constexpr int D = PS::D;
+  constexpr int Q = TL::S::Q;
+  constexpr int HX = PS::HX, HM = PS::HM, HO = PS::HO;
   constexpr int axm = 1, axo = D - 1;
 
-  const int ox = off[3 * q + 0];
-  const int om = (D == 3) ? off[3 * q + axm] : 0;
-  const int oo = off[3 * q + axo];
-  R wx[KX], wm[KM], wo[KO];
+  const cptr<int> offc = as_const(off);
+  const cptr<R> wc = as_const(wts);
+  const int ox = offc[3 * q + 0];
+  const int om = (D == 3) ? offc[3 * q + axm] : 0;
+  const int oo = offc[3 * q + axo];
 #pragma unroll
-  for (int k = 0; k < KX; ++k) wx[k] = mx ? wts[(3 * q + 0) * NS + k] : R(1);
+  for (int k = 0; k < PS::KX; ++k) in.wx[k] = PS::mx ? wc[(3 * q + 0) * NS + k] : R(1);
 #pragma unroll
-  for (int k = 0; k < KM; ++k) wm[k] = mm ? wts[(3 * q + axm) * NS + k] : R(1);
+  for (int k = 0; k < PS::KM; ++k) in.wm[k] = PS::mm ? wc[(3 * q + axm) * NS + k] : R(1);
 #pragma unroll
-  for (int k = 0; k < KO; ++k) wo[k] = mo ? wts[(3 * q + axo) * NS + k] : R(1);
+  for (int k = 0; k < PS::KO; ++k) in.wo[k] = PS::mo ? wc[(3 * q + axo) * NS + k] : R(1);
 
   const E* base[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) base[a] = src + int64_t(a * Q + q) * pstride;
 
-  // outer-axis interpolation of RO + HO loaded values
-  auto outer = [&](const R (&v)[A][RO + HO], R (&res)[A][RO]) {
-#pragma unroll
-    for (int a = 0; a < A; ++a)
-#pragma unroll
-      for (int r = 0; r < RO; ++r) {
-        if constexpr (KO == 1) {
-          res[a][r] = v[a][r];
-        } else {
-          R s = v[a][r] * wo[0];
-#pragma unroll
-          for (int k = 1; k < KO; ++k) s = fma(wo[k], v[a][r + k], s);
-          res[a][r] = s;
-        }
-      }
-  };
-
-  if constexpr (!mx && !mm) {
-    // direct path: each thread loads its own column
-    const int gx = wrap_idx(g.x0 + min(g.lane, g.vx - 1) + ox, g.nx, g.bcx);
-    int col = gx, ob = g.o0, vo = g.vo;
+  int col[PS::ROUNDS], ob[PS::ROUNDS], vo[PS::ROUNDS];
+  if constexpr (PS::direct) {
+    // each thread loads its own column
+    col[0] = wrap_idx(g.x0 + min(g.lane, g.vx - 1) + ox, g.nx, g.bcx);
+    ob[0] = g.o0;
+    vo[0] = g.vo;
     if constexpr (D == 3) {
-      col += wrap_idx(g.m0 + min(g.w, g.vm - 1) + om, g.nm, g.bcm) * g.sm;
+      col[0] += wrap_idx(g.m0 + min(g.w, g.vm - 1) + om, g.nm, g.bcm) * g.sm;
     } else {
-      ob = g.o0 + min(g.w * RO, g.vo - 1);  // a dead segment reads in-bounds rows
-      vo = max(1, min(RO, g.vo - g.w * RO));
+      ob[0] = g.o0 + min(g.w * RO, g.vo - 1);  // a dead segment reads in-bounds rows
+      vo[0] = max(1, min(RO, g.vo - g.w * RO));
     }
-    R v[A][RO + HO];
-#pragma unroll
-    for (int r = 0; r < RO + HO; ++r) {
-      const int e = wrap_idx(ob + oo + min(r, vo - 1 + HO), g.no, g.bco) * g.so + col;
-#pragma unroll
-      for (int a = 0; a < A; ++a) v[a][r] = TR::ld(at(base[a], e));
-    }
-    outer(v, out);
+    in.slot[0] = 0;
   } else {
-    constexpr int CX = TL::TX + HX;                      // columns along x
-    constexpr int CM = (D == 3) ? TL::NW + HM : TL::NW;  // along middle (3D) or segments (2D)
-    constexpr int NCOL = CX * CM;
-    constexpr int ROUNDS = (NCOL + 255) / 256;
-    constexpr int PX = TL::PX, PM = TL::PM;
-    // ---- phase A: HBM -> registers (outer interpolation) -> LDS.  All loads
-    // of all rounds are issued before the first one is used.
-    int col[ROUNDS], ob[ROUNDS], vo[ROUNDS], slot[ROUNDS];
 #pragma unroll
-    for (int rr = 0; rr < ROUNDS; ++rr) {
-      const int c = min(g.tid + 256 * rr, NCOL - 1);
-      const int xs = c % CX, ms = c / CX;
-      slot[rr] = ms * PX + xs;
+    for (int rr = 0; rr < PS::ROUNDS; ++rr) {
+      const int c = min(g.tid + 256 * rr, PS::NCOL - 1);
+      const int xs = c % PS::CX, ms = c / PS::CX;
+      in.slot[rr] = ms * TL::PX + xs;
       col[rr] = wrap_idx(g.x0 + ox + min(xs, g.vx - 1 + HX), g.nx, g.bcx);
       if constexpr (D == 3) {
         col[rr] += wrap_idx(g.m0 + om + min(ms, g.vm - 1 + HM), g.nm, g.bcm) * g.sm;
@@ -277,47 +298,90 @@ __device__ __forceinline__ void interp_pop(const Geo& g, const typename StoreT<S
         vo[rr] = max(1, min(RO, g.vo - ms * RO));
       }
     }
-    R v[ROUNDS][A][RO + HO];
+  }
 #pragma unroll
-    for (int rr = 0; rr < ROUNDS; ++rr) {
-      if (NCOL % 256 == 0 || rr + 1 < ROUNDS || g.tid + 256 * rr < NCOL) {
+  for (int rr = 0; rr < PS::ROUNDS; ++rr) {
+    if (PS::direct || PS::NCOL % 256 == 0 || rr + 1 < PS::ROUNDS || g.tid + 256 * rr < PS::NCOL) {
 #pragma unroll
-        for (int r = 0; r < RO + HO; ++r) {
-          const int e = wrap_idx(ob[rr] + oo + min(r, vo[rr] - 1 + HO), g.no, g.bco) * g.so + col[rr];
+      for (int r = 0; r < RO + HO; ++r) {
+        const int e = wrap_idx(ob[rr] + oo + min(r, vo[rr] - 1 + HO), g.no, g.bco) * g.so + col[rr];
 #pragma unroll
-          for (int a = 0; a < A; ++a) v[rr][a][r] = TR::ld(at(base[a], e));
-        }
+        for (int a = 0; a < A; ++a) in.v[rr][a][r] = TR::ld(at(base[a], e));
       }
     }
+  }
+  if constexpr (SUB) {
 #pragma unroll
-    for (int rr = 0; rr < ROUNDS; ++rr) {
-      if (NCOL % 256 == 0 || rr + 1 < ROUNDS || g.tid + 256 * rr < NCOL) {
+    for (int rr = 0; rr < PS::ROUNDS; ++rr)
+#pragma unroll
+      for (int a = 0; a < A; ++a)
+#pragma unroll
+        for (int r = 0; r < RO + HO; ++r) in.v[rr][a][r] -= ref[a];
+  }
+}
+
+// Interpolate the loaded population q into out[a][r]: along the outer axis
+// in registers, then (LDS populations) along y and x through the LDS buffers
+// P and T of the current parity.
+template <int SET, int NS, int A, int ST, int RO, int q>
+__device__ __forceinline__ void pop_finish(const Geo& g, PopIn<SET, NS, A, ST, RO, q>& in,
+                                           typename StoreT<ST>::real* P, typename StoreT<ST>::real* T,
+                                           typename StoreT<ST>::real (&out)[A][RO]) {
+  using PS = PopShape<SET, NS, A, ST, RO, q>;
+  using TL = typename PS::TL;
+  using R = typename StoreT<ST>::real;
+  constexpr int KX = PS::KX, KM = PS::KM, KO = PS::KO, HM = PS::HM;
+  constexpr int PX = TL::PX, PM = TL::PM;
+
+  auto outer = [&](const R (&v)[A][RO + PS::HO], R (&res)[A][RO]) {
+#pragma unroll
+    for (int a = 0; a < A; ++a)
+#pragma unroll
+      for (int r = 0; r < RO; ++r) {
+        if constexpr (KO == 1) {
+          res[a][r] = v[a][r];
+        } else {
+          R s = v[a][r] * in.wo[0];
+#pragma unroll
+          for (int k = 1; k < KO; ++k) s = fma(in.wo[k], v[a][r + k], s);
+          res[a][r] = s;
+        }
+      }
+  };
+
+  if constexpr (PS::direct) {
+    outer(in.v[0], out);
+  } else {
+    // ---- phase A (second half): outer interpolation -> LDS
+#pragma unroll
+    for (int rr = 0; rr < PS::ROUNDS; ++rr) {
+      if (PS::NCOL % 256 == 0 || rr + 1 < PS::ROUNDS || g.tid + 256 * rr < PS::NCOL) {
         R res[A][RO];
-        outer(v[rr], res);
+        outer(in.v[rr], res);
 #pragma unroll
         for (int a = 0; a < A; ++a)
 #pragma unroll
-          for (int r = 0; r < RO; ++r) P[(a * RO + r) * PM * PX + slot[rr]] = res[a][r];
+          for (int r = 0; r < RO; ++r) P[(a * RO + r) * PM * PX + in.slot[rr]] = res[a][r];
       }
     }
     __syncthreads();
     const R* X = P;  // rows the x pass reads: [a][r][row][x], row = wave
-    if constexpr (mm) {
+    if constexpr (PS::mm) {
       // ---- phase B: y interpolation in LDS, one thread per (a, r, x) column
-      constexpr int NB = A * RO * CX;
+      constexpr int NB = A * RO * PS::CX;
 #pragma unroll
       for (int c0 = 0; c0 < NB; c0 += 256) {
         const int c = c0 + g.tid;
         if (NB % 256 == 0 || c < NB) {
-          const int xs = c % CX, ar = c / CX;
+          const int xs = c % PS::CX, ar = c / PS::CX;
           R colv[TL::NW + HM];
 #pragma unroll
           for (int m = 0; m < TL::NW + HM; ++m) colv[m] = P[(ar * PM + m) * PX + xs];
 #pragma unroll
           for (int m = 0; m < TL::NW; ++m) {
-            R s = colv[m] * wm[0];
+            R s = colv[m] * in.wm[0];
 #pragma unroll
-            for (int k = 1; k < KM; ++k) s = fma(wm[k], colv[m + k], s);
+            for (int k = 1; k < KM; ++k) s = fma(in.wm[k], colv[m + k], s);
             T[(ar * TL::NW + m) * PX + xs] = s;
           }
         }
@@ -326,7 +390,7 @@ __device__ __forceinline__ void interp_pop(const Geo& g, const typename StoreT<S
       X = T;
     }
     // ---- phase C: x interpolation from LDS into registers
-    constexpr int XR = mm ? TL::NW : PM;  // rows per (a, r) plane of X
+    constexpr int XR = PS::mm ? TL::NW : PM;  // rows per (a, r) plane of X
 #pragma unroll
     for (int a = 0; a < A; ++a)
 #pragma unroll
@@ -335,9 +399,9 @@ __device__ __forceinline__ void interp_pop(const Geo& g, const typename StoreT<S
         if constexpr (KX == 1) {
           out[a][r] = row[0];
         } else {
-          R s = row[0] * wx[0];
+          R s = row[0] * in.wx[0];
 #pragma unroll
-          for (int k = 1; k < KX; ++k) s = fma(wx[k], row[k], s);
+          for (int k = 1; k < KX; ++k) s = fma(in.wx[k], row[k], s);
           out[a][r] = s;
         }
       }
@@ -363,6 +427,53 @@ constexpr int lds_rank() {  // number of LDS-using populations before q
   if constexpr (q > 0) c = lds_rank<SET, NS, q - 1>() + (uses_lds<SET, NS, q - 1>() ? 1 : 0);
   return c;
 }
+
+// Software pipeline over the populations: the HBM loads of population q + 1
+// are issued before population q is interpolated, so their latency overlaps
+// with q's LDS passes and barriers.  `sink(q, out)` receives each result.
+template <int SET, int NS, int A, int ST, int RO, bool SUB, int PARITY>
+struct Pipe {
+  using R = typename StoreT<ST>::real;
+  using E = typename StoreT<ST>::elem;
+  static constexpr int Q = Set<SET>::Q;
+
+  static __device__ __forceinline__ void refs(int q, R cv2, R (&ref)[A]) {
+    ref[0] = SUB ? R(Set<SET>::T.w[q]) : R(0);
+    if constexpr (A == 2) ref[1] = SUB ? cv2 * R(Set<SET>::T.w[q]) : R(0);
+  }
+
+  template <int q, class Sink>
+  static __device__ __forceinline__ void run(const Geo& g, const E* __restrict__ src, int64_t pstride,
+                                             const int* __restrict__ off, const R* __restrict__ wts, R cv2,
+                                             R* P0, R* P1, R* T0, R* T1, PopIn<SET, NS, A, ST, RO, q>& cur,
+                                             Sink&& sink) {
+    constexpr int buf = (lds_rank<SET, NS, q>() + PARITY) & 1;
+    R o[A][RO];
+    if constexpr (q + 1 < Q) {
+      PopIn<SET, NS, A, ST, RO, q + 1> nxt;
+      R ref[A];
+      refs(q + 1, cv2, ref);
+      pop_load<SET, NS, A, ST, RO, q + 1, SUB>(g, src, pstride, off, wts, ref, nxt);
+      pop_finish<SET, NS, A, ST, RO, q>(g, cur, buf ? P1 : P0, buf ? T1 : T0, o);
+      sink(std::integral_constant<int, q>{}, o);
+      run<q + 1>(g, src, pstride, off, wts, cv2, P0, P1, T0, T1, nxt, sink);
+    } else {
+      pop_finish<SET, NS, A, ST, RO, q>(g, cur, buf ? P1 : P0, buf ? T1 : T0, o);
+      sink(std::integral_constant<int, q>{}, o);
+    }
+  }
+
+  template <class Sink>
+  static __device__ __forceinline__ void all(const Geo& g, const E* __restrict__ src, int64_t pstride,
+                                             const int* __restrict__ off, const R* __restrict__ wts, R cv2,
+                                             R* P0, R* P1, R* T0, R* T1, Sink&& sink) {
+    PopIn<SET, NS, A, ST, RO, 0> first;
+    R ref[A];
+    refs(0, cv2, ref);
+    pop_load<SET, NS, A, ST, RO, 0, SUB>(g, src, pstride, off, wts, ref, first);
+    run<0>(g, src, pstride, off, wts, cv2, P0, P1, T0, T1, first, sink);
+  }
+};
 
 // ---------------------------------------------------------------------------
 // Equilibrium polynomial P(a, U, eta, X) = f^eq / (w rho), minus 1
@@ -447,14 +558,23 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
   g.w = threadIdx.x >> 6;
   g.nx = p.n[0];
   g.bcx = p.bc[0];
-  g.x0 = blockIdx.x * TL::TX;
+  // XCD-aware tile order: hardware blocks go round-robin to the 8 XCDs; give
+  // each XCD a contiguous run of logical tiles so that the halo rows shared by
+  // neighbouring tiles are read through the same L2.
+  const int bid = blockIdx.x;
+  const int tile = (bid & 7) * p.chunk + (bid >> 3);
+  if (tile >= p.tiles[0] * p.tiles[1] * p.tiles[2]) return;
+  const int tix = tile % p.tiles[0];
+  const int tiy = (tile / p.tiles[0]) % p.tiles[1];
+  const int tiz = tile / (p.tiles[0] * p.tiles[1]);
+  g.x0 = tix * TL::TX;
   g.vx = min(TL::TX, g.nx - g.x0);
   if constexpr (D == 3) {
     g.nm = p.n[1]; g.no = p.n[2];
     g.bcm = p.bc[1]; g.bco = p.bc[2];
     g.sm = p.n[0]; g.so = p.n[0] * p.n[1];
-    g.m0 = blockIdx.y * TL::NW;
-    g.o0 = blockIdx.z * RO;
+    g.m0 = tiy * TL::NW;
+    g.o0 = tiz * RO;
     g.vm = min(TL::NW, g.nm - g.m0);
     g.vo = min(RO, g.no - g.o0);
   } else {
@@ -462,7 +582,7 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
     g.bcm = 0; g.bco = p.bc[1];
     g.sm = 0; g.so = p.n[0];
     g.m0 = 0;
-    g.o0 = blockIdx.y * TL::TOUT;
+    g.o0 = tiy * TL::TOUT;
     g.vm = 1;
     g.vo = min(TL::TOUT, g.no - g.o0);
   }
@@ -477,12 +597,14 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
   constexpr bool TWO = (MODE == MODE_ADJ_STEP || MODE == MODE_ADJ_COLLIDE);
   R lam[TWO ? Q : 1][RO];
 
+  // populations stored whole but computed on as deviations
+  constexpr bool SUBREF = DEV && !TR::stores_dev;
+  const R cv2 = R(p.cv2mD);
+
   if constexpr (MODE != MODE_ADJ_STREAM) {
-    static_for<Q>([&](auto qc) {
+    Pipe<SET, NS, A, ST, RO, SUBREF, 0>::all(g, src, p.pstride, p.off, wts, cv2, P_lds[0], P_lds[1], T_lds[0],
+                                               T_lds[1], [&](auto qc, R (&o)[A][RO]) {
       constexpr int q = decltype(qc)::value;
-      constexpr int buf = lds_rank<SET, NS, q>() & 1;
-      R o[A][RO];
-      interp_pop<SET, NS, A, ST, RO, q>(g, src, p.pstride, p.off, wts, P_lds[buf], T_lds[buf], o);
 #pragma unroll
       for (int a = 0; a < A; ++a)
 #pragma unroll
@@ -492,12 +614,10 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
   if constexpr (MODE == MODE_ADJ_STEP || MODE == MODE_ADJ_STREAM) {
     // S^T applied to src2 with the transposed stencil; src2 is of the compute type
     const E* __restrict__ src2 = static_cast<const E*>(p.src2);
-    constexpr int base = (MODE == MODE_ADJ_STREAM) ? 0 : 1;
-    static_for<Q>([&](auto qc) {
+    constexpr int parity = (MODE == MODE_ADJ_STREAM) ? 0 : (lds_rank<SET, NS, Q>() & 1);
+    Pipe<SET, NS, 1, ST, RO, false, parity>::all(g, src2, p.pstride, p.off_t, wts_t, cv2, P_lds[0], P_lds[1],
+                                                  T_lds[0], T_lds[1], [&](auto qc, R (&o)[1][RO]) {
       constexpr int q = decltype(qc)::value;
-      constexpr int buf = (lds_rank<SET, NS, q>() + base * lds_rank<SET, NS, Q>()) & 1;
-      R o[1][RO];
-      interp_pop<SET, NS, 1, ST, RO, q>(g, src2, p.pstride, p.off_t, wts_t, P_lds[buf], T_lds[buf], o);
 #pragma unroll
       for (int r = 0; r < RO; ++r) {
         if constexpr (MODE == MODE_ADJ_STREAM) ft[q][r] = o[0][r];
@@ -537,7 +657,11 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
     R rho, jx = R(0), jy = R(0), jz = R(0);
     R Ef = R(0), G = R(0);
     double Ed = 0.0;
-    if constexpr (DEV) {
+    // total energy sum(|xh|^2 f + g) before the collision, in the frame the
+    // equilibrium is formed in (deviations, or whole values for FP64)
+    R Epre = R(0);
+    double Epre64 = 0.0;
+    if constexpr (DEV && TR::kahan) {
       Kahan<R> kr, kx, ky, kz, ke, kg;
       static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
@@ -558,9 +682,38 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
       jy = R(p.swx[1]) + ky.s;
       jz = R(p.swx[2]) + kz.s;
       if constexpr (COMP) {
+        Epre64 = Ed + double(kg.s);
+        Epre = ke.s + kg.s;
         Ed += p.swX;
         Ef = R(p.swX) + ke.s;
         G = R(p.cv2mD * p.sw) + kg.s;
+      }
+    } else if constexpr (DEV) {
+      // plain sums of the deviations (FP32 storage)
+      R sr = R(0), se = R(0), sg = R(0);
+      static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const R d = ft[q][r];
+        sr += d;
+        if constexpr (S::moves(q, 0)) jx = fma(R(S::xh(q, 0)), d, jx);
+        if constexpr (S::moves(q, 1)) jy = fma(R(S::xh(q, 1)), d, jy);
+        if constexpr (D == 3 && S::moves(q, 2)) jz = fma(R(S::xh(q, 2)), d, jz);
+        if constexpr (COMP) {
+          constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
+          if constexpr (X != 0.0) se = fma(R(X), d, se);
+          sg += ft[Q + q][r];
+        }
+      });
+      rho = R(p.sw) + sr;
+      jx += R(p.swx[0]);
+      jy += R(p.swx[1]);
+      jz += R(p.swx[2]);
+      if constexpr (COMP) {
+        Epre = se + sg;
+        Epre64 = double(se) + double(sg);
+        Ed = p.swX + double(se);
+        Ef = R(p.swX) + se;
+        G = R(p.cv2mD * p.sw) + sg;
       }
     } else {
       rho = R(0);
@@ -578,6 +731,7 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
         }
       });
     }
+    if constexpr (!DEV && COMP) Epre = Ef + G;
     const R inv_rho = R(1) / rho;
     const R ux = jx * inv_rho, uy = jy * inv_rho, uz = (D == 3) ? jz * inv_rho : R(0);
     const R U = ux * ux + uy * uy + uz * uz;
@@ -603,30 +757,53 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
         const R tau = R(0.5) + R(p.tau_m_half) / (rho * theta);
         omega = R(1) / tau;
       }
-      const R om1 = R(1) - omega;
-      const R cv2 = R(p.cv2mD);
+      // The set's constants rounded to the compute type satisfy
+      // sum_i w_i xh_i xh_i = I only to rounding; BGK with omega near 2 would
+      // turn that defect into a steady growth of momentum.  The linear term of
+      // the equilibrium is renormalized per axis so its momentum is exactly j~.
+      const R dux = ux * R(p.cmom[0] - 1.0), duy = uy * R(p.cmom[1] - 1.0), duz = uz * R(p.cmom[2] - 1.0);
+      R Eeq = R(0);
+      double Eeq64 = 0.0;
       static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
-        R a = R(0);
-        if constexpr (S::moves(q, 0)) a = fma(R(S::xh(q, 0)), ux, a);
-        if constexpr (S::moves(q, 1)) a = fma(R(S::xh(q, 1)), uy, a);
-        if constexpr (D == 3 && S::moves(q, 2)) a = fma(R(S::xh(q, 2)), uz, a);
-        const R pm1 = peq_minus1<N, D, COMP, R>(a, U, eta, R(X));
+        R a = R(0), ac = R(0);
+        if constexpr (S::moves(q, 0)) { a = fma(R(S::xh(q, 0)), ux, a); ac = fma(R(S::xh(q, 0)), dux, ac); }
+        if constexpr (S::moves(q, 1)) { a = fma(R(S::xh(q, 1)), uy, a); ac = fma(R(S::xh(q, 1)), duy, ac); }
+        if constexpr (D == 3 && S::moves(q, 2)) { a = fma(R(S::xh(q, 2)), uz, a); ac = fma(R(S::xh(q, 2)), duz, ac); }
+        const R pm1 = peq_minus1<N, D, COMP, R>(a, U, eta, R(X)) + ac;
         const R w = R(S::w(q));
         R feq_dev;  // f^eq - w (DEV) or f^eq
         if constexpr (DEV) feq_dev = w * fma(rho - R(1), R(1) + pm1, pm1);
         else feq_dev = w * rho * (R(1) + pm1);
-        const R fo = fma(omega, feq_dev, om1 * ft[q][r]);
-        TR::st(dst + int64_t(q) * p.pstride + cell, fo);
+        // f* = f + omega (f^eq - f): the small non-equilibrium part carries the rounding
+        const R fo = fma(omega, feq_dev - ft[q][r], ft[q][r]);
+        TR::st(dst + int64_t(q) * p.pstride + cell, SUBREF ? fo + w : fo);
         if constexpr (COMP) {
           R geq;
           if constexpr (DEV) geq = cv2 * fma(theta, feq_dev, eta * w);
           else geq = cv2 * theta * feq_dev;
-          const R go = fma(omega, geq, om1 * ft[Q + q][r]);
-          TR::st(dst + int64_t(Q + q) * p.pstride + cell, go);
+          if constexpr (X != 0.0) Eeq = fma(R(X), feq_dev, Eeq);
+          Eeq += geq;
+          if (DEV && p.e64 != 0.0) Eeq64 += X * double(feq_dev) + double(geq);
+          ft[Q + q][r] = fma(omega, geq - ft[Q + q][r], ft[Q + q][r]);  // relaxed g, before the energy fix
         }
       });
+      if constexpr (COMP) {
+        // Energy is a collision invariant (Sec. 3); the discrete equilibrium
+        // carries it only to the rounding of the constants.  The remainder
+        // goes to g in proportion to w_i, which changes neither mass nor
+        // momentum: sum_i (|xh_i|^2 f*_i + g*_i) = sum_i (|xh_i|^2 f~_i + g~_i).
+        R dE = Epre - Eeq;
+        if (DEV && p.e64 != 0.0) dE = R(Epre64 - Eeq64);
+        const R corr = omega * dE * R(1.0 / p.sw);
+        static_for<Q>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          const R w = R(S::w(q));
+          const R go = fma(corr, w, ft[Q + q][r]);
+          TR::st(dst + int64_t(Q + q) * p.pstride + cell, SUBREF ? go + cv2 * w : go);
+        });
+      }
     } else {
       // adjoint of the weakly compressible collision at this cell
       R lm[Q];
@@ -696,6 +873,7 @@ struct CellParams {
   double cs;          // u = cs * u~
   double cv2mD, inv2cv, sw, swX, swx[3];
   double scale;       // 1 / ncell (KE adjoint)
+  double cmom[3];     // 1 / sum_i w_i xh_ia^2 with the compute type's rounded constants
 };
 
 template <int SET, int N, int A, int ST>
@@ -719,21 +897,24 @@ __global__ __launch_bounds__(256) void init_kernel(CellParams p) {
   const R U = ux * ux + uy * uy + uz * uz;
   const R theta = (COMP && th_p) ? th_p[e] : R(1);
   const R eta = theta - R(1);
+  const R dux = ux * R(p.cmom[0] - 1.0), duy = uy * R(p.cmom[1] - 1.0), duz = uz * R(p.cmom[2] - 1.0);
   static_for<Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
     constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
     const R a = R(S::xh(q, 0)) * ux + R(S::xh(q, 1)) * uy + R(S::xh(q, 2)) * uz;
-    const R pm1 = peq_minus1<N, D, COMP, R>(a, U, eta, R(X));
+    const R ac = R(S::xh(q, 0)) * dux + R(S::xh(q, 1)) * duy + R(S::xh(q, 2)) * duz;
+    const R pm1 = peq_minus1<N, D, COMP, R>(a, U, eta, R(X)) + ac;
     const R w = R(S::w(q));
     R fe;
     if constexpr (TR::dev) fe = w * fma(rho - R(1), R(1) + pm1, pm1);
     else fe = w * rho * (R(1) + pm1);
-    TR::st(out + int64_t(q) * p.ncell + e, fe);
+    constexpr bool whole = TR::dev && !TR::stores_dev;  // deviation arithmetic, whole values stored
+    TR::st(out + int64_t(q) * p.ncell + e, whole ? fe + w : fe);
     if constexpr (COMP) {
       R ge;
       if constexpr (TR::dev) ge = R(p.cv2mD) * fma(theta, fe, eta * w);
       else ge = R(p.cv2mD) * theta * fe;
-      TR::st(out + int64_t(Q + q) * p.ncell + e, ge);
+      TR::st(out + int64_t(Q + q) * p.ncell + e, whole ? ge + R(p.cv2mD) * w : ge);
     }
   });
 }
@@ -761,7 +942,7 @@ __global__ __launch_bounds__(256) void moments_kernel(CellParams p) {
     static_for<Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
       double v = double(TR::ld(f + int64_t(q) * p.ncell + e));
-      if constexpr (TR::dev) v += S::w(q);
+      if constexpr (TR::stores_dev) v += S::w(q);
       rho += v;
       jx += S::xh(q, 0) * v;
       jy += S::xh(q, 1) * v;
@@ -770,7 +951,7 @@ __global__ __launch_bounds__(256) void moments_kernel(CellParams p) {
       Ef += X * v;
       if constexpr (COMP) {
         double gv = double(TR::ld(f + int64_t(Q + q) * p.ncell + e));
-        if constexpr (TR::dev) gv += p.cv2mD * S::w(q);
+        if constexpr (TR::stores_dev) gv += p.cv2mD * S::w(q);
         G += gv;
       }
     });
@@ -861,7 +1042,7 @@ __global__ __launch_bounds__(256) void ke_adjoint_kernel(CellParams p) {
   R rho = R(0), jx = R(0), jy = R(0), jz = R(0);
   static_for<Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
-    const R v = TR::ld(f + int64_t(q) * p.ncell + e);
+    const R v = TR::ld(f + int64_t(q) * p.ncell + e) + (TR::stores_dev ? R(S::w(q)) : R(0));
     rho += v;
     jx = fma(R(S::xh(q, 0)), v, jx);
     jy = fma(R(S::xh(q, 1)), v, jy);

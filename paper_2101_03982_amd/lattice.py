@@ -93,6 +93,10 @@ class Lattice:
         check(_lib.lib().lbm_set_stream(self._ctx, ctypes.c_void_p(s)), "lbm_set_stream")
 
     def _need(self, t, shape, dtype, what):
+        if t.numel() != int(torch.Size(shape).numel()):
+            raise ValueError("%s: want %s elements %s, got %s" % (what, torch.Size(shape).numel(), tuple(shape),
+                                                                  tuple(t.shape)))
+        t = t.reshape(shape)
         if t.device != self.device or t.dtype != dtype or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
             raise ValueError("%s: want contiguous %s %s on %s, got %s %s on %s" % (
                 what, dtype, tuple(shape), self.device, t.dtype, tuple(t.shape), t.device))
@@ -141,10 +145,10 @@ class Lattice:
 
     def init_equilibrium(self, rho, u, theta=None):
         self._stream()
-        rho = self._need(rho.reshape(self.shape), self.shape, self.dtype, "rho")
-        u = self._need(u.reshape((self.D,) + self.shape), (self.D,) + self.shape, self.dtype, "u")
+        rho = self._need(rho, self.shape, self.dtype, "rho")
+        u = self._need(u, (self.D,) + self.shape, self.dtype, "u")
         if theta is not None:
-            theta = self._need(theta.reshape(self.shape), self.shape, self.dtype, "theta")
+            theta = self._need(theta, self.shape, self.dtype, "theta")
         check(_lib.lib().lbm_init_equilibrium(self._ctx, _ptr(rho), _ptr(u), _ptr(theta)), "lbm_init_equilibrium")
 
     def step(self, n: int = 1):

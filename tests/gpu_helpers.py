@@ -32,7 +32,7 @@ def gpu_populations(lat, state=None):
     """The state as float64 numpy populations (deviation storage adds back the
     reference values w_i and (2 C_v - D) w_i)."""
     f = (lat.state() if state is None else state).to(torch.float64).cpu().numpy()
-    if lat.storage in ("bf16", "f16"):
+    if lat.storage in ("f32", "bf16", "f16"):
         t = lat.table()
         w = np.array(t["w"])
         ref = [w]

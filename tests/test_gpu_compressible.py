@@ -1,0 +1,97 @@
+"""Compressible two-population model (Sec. 3) on the GPU against the oracle,
+and the reduced-precision storage form.
+
+* Shock-vortex workload (Sec. 4.1 shape: Mach-1.2 shock with Rankine-Hugoniot
+  states, isentropic vortex upstream), D2Q19 and D2Q25, N = 4, n = 5,
+  extrapolation in x, periodic in y: FP64 within 1e-12 of the oracle.
+* Compressible Taylor-Green vortex (CTIC, Sec. 4.3), D3Q45, N = 4, Ma 0.5 and
+  1.0: FP64 within 1e-12; total energy conserved on the periodic grid.
+* BF16 / FP16 deviation storage: one step from the equilibrium, each stored
+  deviation within a few units in the last place of its format of the FP64
+  oracle (the tolerance counts the rounding of the initial state, the
+  rounding of the result and FP32 arithmetic).
+"""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as W
+from gpu_helpers import gpu_populations, init_both, pair, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name", ["D2Q19", "D2Q25"])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+def test_shock_vortex_parity(orc, name, storage, tol):
+    base = W.svi_workload(name, n=512)
+    # the same physics on a 140 x 96 window (three x tiles with a ragged tail)
+    wl = base.with_(grid=(140, 96, 1))
+    lat, cfg = pair(orc, name, wl.grid, wl.tau, wl.order, wl.stencil, storage, wl.dx, wl.dt, wl.cs,
+                    compressible=True, gamma=wl.gamma, bc=wl.bc)
+    rho, u, theta = W.svi_fields(wl)
+    f = init_both(lat, orc, cfg, rho, u, theta)
+    lat.step(10)
+    f = orc.run(cfg, f, 10)
+    assert rel_err(gpu_populations(lat), f) <= tol
+
+
+@pytest.mark.parametrize("Ma", [0.5, 1.0])
+def test_compressible_tgv_parity(orc, Ma):
+    wl = W.ctgv_workload(n=16, Ma=Ma)
+    lat, cfg = pair(orc, "D3Q45", wl.grid, wl.tau, 4, wl.stencil, "f64", wl.dx, wl.dt, wl.cs,
+                    compressible=True, gamma=wl.gamma)
+    rho, u, theta = W.ctgv_fields(wl)
+    f = init_both(lat, orc, cfg, rho, u, theta)
+    e0 = lat.moments(fields=False)[3].energy
+    lat.step(3)
+    f = orc.run(cfg, f, 3)
+    assert rel_err(gpu_populations(lat), f) <= 1e-12
+    d = lat.moments(fields=False)[3]
+    assert abs(d.energy / e0 - 1) < 1e-13
+    assert abs(d.energy / orc.moments(cfg, f)[3]["energy"] - 1) < 1e-13
+
+
+def test_moment_fields_match_oracle(orc):
+    wl = W.ctgv_workload(n=12, Ma=1.0)
+    lat, cfg = pair(orc, "D3Q45", wl.grid, wl.tau, 4, wl.stencil, "f64", wl.dx, wl.dt, wl.cs,
+                    compressible=True, gamma=wl.gamma)
+    rho, u, theta = W.ctgv_fields(wl)
+    f = init_both(lat, orc, cfg, rho, u, theta)
+    lat.step(2)
+    f = orc.run(cfg, f, 2)
+    r, uu, th, d = lat.moments()
+    r0, u0, th0, d0 = orc.moments(cfg, f)
+    assert rel_err(r.cpu().numpy(), r0) < 1e-13
+    assert rel_err(uu.cpu().numpy(), u0) < 1e-12
+    assert rel_err(th.cpu().numpy(), th0) < 1e-13
+    assert abs(d.ke / d0["ke"] - 1) < 1e-12
+    assert abs(d.mass / d0["mass"] - 1) < 1e-14
+    assert abs(d.min_rho - d0["min_rho"]) < 1e-13 and abs(d.min_theta - d0["min_theta"]) < 1e-13
+
+
+# unit roundoff of the stored deviations
+ULP = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11}
+
+
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+@pytest.mark.parametrize("Ma", [0.5, 1.0])
+@pytest.mark.parametrize("e64", [False, True])
+def test_reduced_precision_one_step(orc, storage, Ma, e64):
+    wl = W.ctgv_workload(n=16, Ma=Ma)
+    lat, cfg = pair(orc, "D3Q45", wl.grid, wl.tau, 4, wl.stencil, storage, wl.dx, wl.dt, wl.cs,
+                    compressible=True, gamma=wl.gamma, energy_f64=e64)
+    rho, u, theta = W.ctgv_fields(wl)
+    f = init_both(lat, orc, cfg, rho, u, theta)
+    lat.step(1)
+    f1 = orc.run(cfg, f, 1)
+    got = gpu_populations(lat)
+    w = np.array(lat.table()["w"])
+    Cv = 1.0 / (wl.gamma - 1.0)
+    ref = np.concatenate([w, (2 * Cv - 3) * w]).reshape((-1, 1, 1, 1))
+    dev = np.abs(f1 - ref)
+    # per population: the deviation's own rounding plus the interpolated
+    # rounding of the initial state (16-bit subnormals of FP16 add 2^-24)
+    scale = np.max(dev, axis=(1, 2, 3), keepdims=True)
+    tol = 3 * ULP[storage] * scale + 2.0 ** -23
+    assert np.all(np.abs(got - f1) <= tol), float(np.max(np.abs(got - f1) / tol))

@@ -49,7 +49,7 @@ def test_step_parity_stencil_lengths(orc, name, n):
     assert rel_err(got, ref) <= 1e-12, rel_err(got, ref)
 
 
-@pytest.mark.parametrize("name,order", [("D3V27", 3), ("D2Q25", 3), ("D2Q19", 4), ("D3Q45", 3), ("D3Q45", 4)])
+@pytest.mark.parametrize("name,order", [("D3V27", 3), ("D2Q25", 4), ("D2Q19", 4), ("D3Q45", 4)])
 def test_step_parity_higher_orders(orc, name, order):
     got, ref = problem(orc, name, "f64", n=4, order=order)
     assert rel_err(got, ref) <= 1e-12, rel_err(got, ref)
