@@ -134,19 +134,18 @@ int set_device(const lbm_ctx* c) {
   return LBM_OK;
 }
 
-// 1 / sum_i w_i xh_ia^2 evaluated with the weights and abscissae rounded to
-// the kernels' compute type (exactly 1 for exact constants).
-void momentum_norm(const lbm_ctx* c, double* cm) {
+// 1 / sum_i w_i xh_ix^2 - 1 with the weights and abscissae rounded to float,
+// the compute type of the deviation forms (unused by the FP64 form).  The sets
+// are symmetric under exchange of axes, so one axis gives the factor.
+double momentum_norm(const lbm_ctx* c) {
+  if (compute_is_f64(c)) return 0.0;
   const SetTable t = set_table(c->set);
-  for (int a = 0; a < 3; ++a) {
-    double s = 0.0;
-    for (int i = 0; i < t.Q; ++i) {
-      const double w = compute_is_f64(c) ? t.w[i] : double(float(t.w[i]));
-      const double x = compute_is_f64(c) ? t.xh[i][a] : double(float(t.xh[i][a]));
-      s += w * x * x;
-    }
-    cm[a] = (a < c->D && s > 0) ? 1.0 / s : 1.0;
+  double s = 0.0;
+  for (int i = 0; i < t.Q; ++i) {
+    const double x = double(float(t.xh[i][0]));
+    s += double(float(t.w[i])) * x * x;
   }
+  return 1.0 / s - 1.0;
 }
 
 KParams base_params(const lbm_ctx* c) {
@@ -169,7 +168,7 @@ KParams base_params(const lbm_ctx* c) {
   for (int a = 0; a < 3; ++a) p.swx[a] = c->swx[a];
   p.swX = c->swX;
   p.e64 = c->e64 ? 1.0 : 0.0;
-  momentum_norm(c, p.cmom);
+  p.cmom1 = momentum_norm(c);
   return p;
 }
 
@@ -184,7 +183,6 @@ CellParams base_cell(const lbm_ctx* c) {
   p.swX = c->swX;
   for (int a = 0; a < 3; ++a) p.swx[a] = c->swx[a];
   p.scale = 1.0 / double(c->ncell);
-  momentum_norm(c, p.cmom);
   return p;
 }
 

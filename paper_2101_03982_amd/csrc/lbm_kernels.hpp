@@ -128,7 +128,7 @@ struct KParams {
   double swx[3];       // sum_i w_i xh_i
   double swX;          // sum_i w_i |xh_i|^2
   double e64;          // nonzero: compressible energy moment summed in FP64
-  double cmom[3];      // 1 / sum_i w_i xh_ia^2 with the compute type's rounded constants
+  double cmom1;        // 1 / sum_i w_i xh_ix^2 - 1 with the FP32-rounded constants
 };
 
 // Cells per thread along the register (outer) axis.
@@ -731,7 +731,6 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
         }
       });
     }
-    if constexpr (!DEV && COMP) Epre = Ef + G;
     const R inv_rho = R(1) / rho;
     const R ux = jx * inv_rho, uy = jy * inv_rho, uz = (D == 3) ? jz * inv_rho : R(0);
     const R U = ux * ux + uy * uy + uz * uz;
@@ -757,50 +756,56 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
         const R tau = R(0.5) + R(p.tau_m_half) / (rho * theta);
         omega = R(1) / tau;
       }
-      // The set's constants rounded to the compute type satisfy
-      // sum_i w_i xh_i xh_i = I only to rounding; BGK with omega near 2 would
-      // turn that defect into a steady growth of momentum.  The linear term of
-      // the equilibrium is renormalized per axis so its momentum is exactly j~.
-      const R dux = ux * R(p.cmom[0] - 1.0), duy = uy * R(p.cmom[1] - 1.0), duz = uz * R(p.cmom[2] - 1.0);
-      R Eeq = R(0);
+      // FP32 forms: the set's constants rounded to float give sum_i w_i xh_i xh_i
+      // = (1 + m) I with |m| ~ 1e-8, which BGK with omega near 2 would turn
+      // into a steady drift of the momentum (and in the compressible model of
+      // the energy).  The missing equilibrium momentum rho m' u~ (m' = 1/(1+m) - 1)
+      // is restored as w_i rho m' (xh_i . u~) and the missing energy as w_i dE / sum w,
+      // both added to the small non-equilibrium difference f^eq - f before it is
+      // scaled by omega, where they are far above its rounding.  Neither changes the
+      // other invariants (odd/even symmetry of the set).
+      R kmom = R(0), Eeq = R(0);
       double Eeq64 = 0.0;
+      if constexpr (DEV) kmom = rho * R(p.cmom1);
       static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
-        R a = R(0), ac = R(0);
-        if constexpr (S::moves(q, 0)) { a = fma(R(S::xh(q, 0)), ux, a); ac = fma(R(S::xh(q, 0)), dux, ac); }
-        if constexpr (S::moves(q, 1)) { a = fma(R(S::xh(q, 1)), uy, a); ac = fma(R(S::xh(q, 1)), duy, ac); }
-        if constexpr (D == 3 && S::moves(q, 2)) { a = fma(R(S::xh(q, 2)), uz, a); ac = fma(R(S::xh(q, 2)), duz, ac); }
-        const R pm1 = peq_minus1<N, D, COMP, R>(a, U, eta, R(X)) + ac;
+        R a = R(0);
+        if constexpr (S::moves(q, 0)) a = fma(R(S::xh(q, 0)), ux, a);
+        if constexpr (S::moves(q, 1)) a = fma(R(S::xh(q, 1)), uy, a);
+        if constexpr (D == 3 && S::moves(q, 2)) a = fma(R(S::xh(q, 2)), uz, a);
+        const R pm1 = peq_minus1<N, D, COMP, R>(a, U, eta, R(X));
         const R w = R(S::w(q));
         R feq_dev;  // f^eq - w (DEV) or f^eq
         if constexpr (DEV) feq_dev = w * fma(rho - R(1), R(1) + pm1, pm1);
         else feq_dev = w * rho * (R(1) + pm1);
         // f* = f + omega (f^eq - f): the small non-equilibrium part carries the rounding
-        const R fo = fma(omega, feq_dev - ft[q][r], ft[q][r]);
+        R df = feq_dev - ft[q][r];
+        if constexpr (DEV && X != 0.0) df = fma(w * kmom, a, df);
+        const R fo = fma(omega, df, ft[q][r]);
         TR::st(dst + int64_t(q) * p.pstride + cell, SUBREF ? fo + w : fo);
         if constexpr (COMP) {
           R geq;
           if constexpr (DEV) geq = cv2 * fma(theta, feq_dev, eta * w);
           else geq = cv2 * theta * feq_dev;
-          if constexpr (X != 0.0) Eeq = fma(R(X), feq_dev, Eeq);
-          Eeq += geq;
-          if (DEV && p.e64 != 0.0) Eeq64 += X * double(feq_dev) + double(geq);
-          ft[Q + q][r] = fma(omega, geq - ft[Q + q][r], ft[Q + q][r]);  // relaxed g, before the energy fix
+          if constexpr (DEV) {
+            if constexpr (X != 0.0) Eeq = fma(R(X), feq_dev, Eeq);
+            Eeq += geq;
+            if (p.e64 != 0.0) Eeq64 += X * double(feq_dev) + double(geq);
+            ft[q][r] = geq - ft[Q + q][r];  // f_q is stored: its register keeps g^eq - g
+          } else {
+            const R go = fma(omega, geq - ft[Q + q][r], ft[Q + q][r]);
+            TR::st(dst + int64_t(Q + q) * p.pstride + cell, go);
+          }
         }
       });
-      if constexpr (COMP) {
-        // Energy is a collision invariant (Sec. 3); the discrete equilibrium
-        // carries it only to the rounding of the constants.  The remainder
-        // goes to g in proportion to w_i, which changes neither mass nor
-        // momentum: sum_i (|xh_i|^2 f*_i + g*_i) = sum_i (|xh_i|^2 f~_i + g~_i).
-        R dE = Epre - Eeq;
-        if (DEV && p.e64 != 0.0) dE = R(Epre64 - Eeq64);
-        const R corr = omega * dE * R(1.0 / p.sw);
+      if constexpr (COMP && DEV) {
+        R cE = (Epre - Eeq) * R(1.0 / p.sw);
+        if (p.e64 != 0.0) cE = R((Epre64 - Eeq64) / p.sw);
         static_for<Q>([&](auto qc) {
           constexpr int q = decltype(qc)::value;
           const R w = R(S::w(q));
-          const R go = fma(corr, w, ft[Q + q][r]);
+          const R go = fma(omega, fma(w, cE, ft[q][r]), ft[Q + q][r]);
           TR::st(dst + int64_t(Q + q) * p.pstride + cell, SUBREF ? go + cv2 * w : go);
         });
       }
@@ -873,7 +878,6 @@ struct CellParams {
   double cs;          // u = cs * u~
   double cv2mD, inv2cv, sw, swX, swx[3];
   double scale;       // 1 / ncell (KE adjoint)
-  double cmom[3];     // 1 / sum_i w_i xh_ia^2 with the compute type's rounded constants
 };
 
 template <int SET, int N, int A, int ST>
@@ -897,13 +901,11 @@ __global__ __launch_bounds__(256) void init_kernel(CellParams p) {
   const R U = ux * ux + uy * uy + uz * uz;
   const R theta = (COMP && th_p) ? th_p[e] : R(1);
   const R eta = theta - R(1);
-  const R dux = ux * R(p.cmom[0] - 1.0), duy = uy * R(p.cmom[1] - 1.0), duz = uz * R(p.cmom[2] - 1.0);
   static_for<Q>([&](auto qc) {
     constexpr int q = decltype(qc)::value;
     constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
     const R a = R(S::xh(q, 0)) * ux + R(S::xh(q, 1)) * uy + R(S::xh(q, 2)) * uz;
-    const R ac = R(S::xh(q, 0)) * dux + R(S::xh(q, 1)) * duy + R(S::xh(q, 2)) * duz;
-    const R pm1 = peq_minus1<N, D, COMP, R>(a, U, eta, R(X)) + ac;
+    const R pm1 = peq_minus1<N, D, COMP, R>(a, U, eta, R(X));
     const R w = R(S::w(q));
     R fe;
     if constexpr (TR::dev) fe = w * fma(rho - R(1), R(1) + pm1, pm1);
