@@ -176,7 +176,8 @@ def precision_form(n=256, steps=1000, machs=(0.5, 1.0)):
         entry = {}
         for st in ("f64", "f32", "bf16", "f16"):
             lat = Lattice("D3Q45", wl.grid, wl.tau, 4, stencil=wl.stencil, storage=st, dx=wl.dx, dt=wl.dt,
-                          cs=wl.cs, compressible=True, gamma=wl.gamma, energy_f64=(st in ("bf16", "f16")),
+                          cs=wl.cs, compressible=True, gamma=wl.gamma,
+                          energy_f64=(st in ("bf16", "f16") and Ma >= 1.0),
                           device="cuda:0")
             dt_ = lat.dtype
             lat.init_equilibrium(torch.from_numpy(rho_np).to("cuda:0", dt_), torch.from_numpy(u_np).to("cuda:0", dt_),
@@ -219,6 +220,105 @@ def precision_form(n=256, steps=1000, machs=(0.5, 1.0)):
         res["Ma%.1f" % Ma] = entry
     res["workload"] = "compressible TGV (CTIC) D3Q45 f+g, N = 4, n = 4, %d^3, Re 1600, %d steps" % (n, steps)
     return res
+
+
+def copy_reference(nbytes):
+    """A plain device-to-device copy moving the same bytes as one launch of
+    the dominant kernel (read + write): the bandwidth a streaming kernel can
+    reach on this machine, beside the nominal peak."""
+    import torch
+
+    n = nbytes // 2 // 4
+    x = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 50
+    e0.record()
+    for _ in range(reps):
+        y.copy_(x)
+    e1.record()
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) / reps * 1e3
+    del x, y
+    torch.cuda.empty_cache()
+    return {"bytes": 2 * n * 4, "us": us, "GBs": 2 * n * 4 / (us * 1e-6) / 1e9}
+
+
+def kernel_time(lat, reps=50):
+    """Average single-launch time (ms) of lat.step(1) with HIP events on the
+    lattice's stream."""
+    import torch
+
+    stream = torch.cuda.current_stream()
+    lat.step(3)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        lat.step(1)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    return sum(e0.elapsed_time(e1) for e0, e1 in evs) / reps
+
+
+def large_grid(sets=("D3Q13", "D3Q27"), n=256):
+    """The same kernels on a 256^3 grid, whose two buffers exceed the 256 MB
+    Infinity Cache, so the bandwidth figure is HBM's."""
+    import torch
+
+    import lbm_inputs as W
+    from paper_2101_03982_amd import Lattice
+
+    out = {}
+    for s in sets:
+        wl = W.tgv3d_workload(s, n=n)
+        lat = Lattice(s, wl.grid, wl.tau, wl.order, stencil=wl.stencil, storage="f32", dx=wl.dx, dt=wl.dt,
+                      cs=wl.cs, device="cuda:0")
+        rho, u, _ = W.tgv3d_fields(wl)
+        lat.init_equilibrium(torch.from_numpy(rho).to("cuda:0", torch.float32),
+                             torch.from_numpy(u).to("cuda:0", torch.float32))
+        ms = kernel_time(lat)
+        gbs = 2 * lat.Q * 4 * wl.ncell / (ms * 1e-3) / 1e9
+        out[s] = {"kernel_ms": ms, "mlups": wl.ncell / (ms * 1e-3) / 1e6, "achieved_GBs": gbs,
+                  "hbm_frac": gbs / HBM_PEAK_GBS}
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    out["workload"] = "3D Taylor-Green vortex %d^3 FP32, n = 4 (working set above the Infinity Cache)" % n
+    return out
+
+
+def svi_throughput(n=512):
+    """Shock-vortex workload (D2Q19 / D2Q25, f + g, N = 4, n = 5, extrapolating
+    in x) at its full 512^2 size: single-launch time per set and storage."""
+    import torch
+
+    import lbm_inputs as W
+    from paper_2101_03982_amd import Lattice
+
+    out = {}
+    for s in ("D2Q19", "D2Q25"):
+        for st in ("f64", "f32"):
+            wl = W.svi_workload(s, n=n, storage=st)
+            lat = Lattice(s, wl.grid, wl.tau, wl.order, stencil=wl.stencil, storage=st, dx=wl.dx, dt=wl.dt,
+                          cs=wl.cs, compressible=True, gamma=wl.gamma,
+                          boundary=("extrapolate", "periodic", "periodic"), device="cuda:0")
+            rho, u, th = W.svi_fields(wl)
+            dt_ = lat.dtype
+            lat.init_equilibrium(torch.from_numpy(rho).to("cuda:0", dt_), torch.from_numpy(u).to("cuda:0", dt_),
+                                 torch.from_numpy(th).to("cuda:0", dt_))
+            ms = kernel_time(lat)
+            b = 8 if st == "f64" else 4
+            gbs = 2 * 2 * lat.Q * b * wl.ncell / (ms * 1e-3) / 1e9
+            out["%s_%s" % (s, st)] = {"kernel_ms": ms, "mlups": wl.ncell / (ms * 1e-3) / 1e6, "achieved_GBs": gbs,
+                                      "hbm_frac": gbs / HBM_PEAK_GBS}
+            lat.close()
+            del lat
+            torch.cuda.empty_cache()
+    out["workload"] = "2D shock-vortex interaction %d^2, D2Q19/D2Q25 f+g, N = 4, n = 5" % n
+    return out
 
 
 def main():
@@ -297,11 +397,13 @@ def main():
     ncells = sum(wl.ncell for _, wl, _ in lats)
     value = ncells * a.steps / elapsed / 1e6
     tr = traffic_for(dominant, a.n)
+    copy = copy_reference(dom["bytes_per_cell"] * a.n ** 3)
     roof = {"bound": "hbm", "kernel": "sl_kernel %s n=4 N=%d FP32 %d^3" % (
         dominant, 3 if dominant == "D3V27" else 2, a.n),
         "achieved": round(dom["achieved_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
         "frac": round(dom["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": tr,
-        "algorithmic_bytes_per_launch": dom["bytes_per_cell"] * a.n ** 3}
+        "algorithmic_bytes_per_launch": dom["bytes_per_cell"] * a.n ** 3,
+        "copy_GBs": round(copy["GBs"], 1), "frac_of_copy": round(dom["achieved_GBs"] / copy["GBs"], 4)}
     out = {
         "metric": "MLUPS & %HBM peak per velocity set; adjoint/forward time; err vs FP64",
         "value": round(value, 1),
@@ -334,6 +436,8 @@ def main():
         torch.cuda.empty_cache()
         out["err_vs_fp64"] = fp64_error(sets, a.n, steps_done, ke32)
         out["adjoint"] = adjoint_cost()
+        out["large_grid"] = large_grid()
+        out["svi"] = svi_throughput()
         torch.cuda.empty_cache()
         out["precision"] = precision_form(a.precision_n, a.precision_steps)
     if not a.no_cpu:

@@ -20,7 +20,7 @@ template <int SET, int NS, int N, int A, int ST, int MODE>
 hipError_t launch_step(const KParams& p, hipStream_t s) {
   using R = typename StoreT<ST>::real;
   constexpr int D = Set<SET>::D;
-  constexpr int RO = cells_per_thread<D, Set<SET>::Q, A, int(sizeof(R)), MODE>();
+  constexpr int RO = cells_per_thread<D, Set<SET>::Q, A, ST, MODE>();
   KParams q = p;
   q.tiles[0] = (p.n[0] + 63) / 64;
   if (D == 3) {

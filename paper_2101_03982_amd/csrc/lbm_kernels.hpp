@@ -57,30 +57,90 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 //      the small deviations instead of the populations;
 // stores_dev: the buffer itself holds deviations (16-bit storage);
 // kahan: moment sums with compensated summation.
+// ldb/stb: buffer accesses at byte offset voff (per lane) + soff (uniform,
+// scalar register), so that a row offset shared by the block costs no vector
+// instruction.  The resource covers one population array (< 4 GiB).
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+template <class E>
+__device__ __forceinline__ rsrc_t make_rsrc(const E* base, int64_t nelem) {
+  // word 3 = 0x00020000: raw (unformatted) 32-bit buffer on gfx9
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<E*>(base), (short)0, int(uint32_t(nelem * int64_t(sizeof(E)))),
+                                           0x00020000);
+}
+
 template <int S> struct StoreT;
 template <> struct StoreT<ST_F64> {
   using elem = double; using real = double;
   static constexpr bool dev = false, stores_dev = false, kahan = false;
   static __device__ __forceinline__ real ld(const elem* p) { return *p; }
   static __device__ __forceinline__ void st(elem* p, real v) { *p = v; }
+  static __device__ __forceinline__ real ldb(rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  }
+  static __device__ __forceinline__ void stb(real v, rsrc_t r, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
+                                          voff, soff, 0);
+  }
+  static __device__ __forceinline__ void ldb2(rsrc_t r, int voff, int soff, real& lo, real& hi) {
+    // (elements copied to scalars first: bit-casting a vector element
+    // directly reinterprets the vector's first element)
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+    const unsigned v0 = v[0], v1 = v[1], v2 = v[2], v3 = v[3];
+    lo = __builtin_bit_cast(double, (uint64_t(v1) << 32) | v0);
+    hi = __builtin_bit_cast(double, (uint64_t(v3) << 32) | v2);
+  }
 };
 template <> struct StoreT<ST_F32> {
   using elem = float; using real = float;
   static constexpr bool dev = true, stores_dev = true, kahan = false;
   static __device__ __forceinline__ real ld(const elem* p) { return *p; }
   static __device__ __forceinline__ void st(elem* p, real v) { *p = v; }
+  static __device__ __forceinline__ real ldb(rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  }
+  static __device__ __forceinline__ void stb(real v, rsrc_t r, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+  }
+  static __device__ __forceinline__ void ldb2(rsrc_t r, int voff, int soff, real& lo, real& hi) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+    const unsigned v0 = v[0], v1 = v[1];  // scalars first, as above
+    lo = __builtin_bit_cast(float, v0);
+    hi = __builtin_bit_cast(float, v1);
+  }
 };
 template <> struct StoreT<ST_BF16> {
   using elem = uint16_t; using real = float;
   static constexpr bool dev = true, stores_dev = true, kahan = true;
   static __device__ __forceinline__ real ld(const elem* p) { return bf16_to_f32(*p); }
   static __device__ __forceinline__ void st(elem* p, real v) { *p = f32_to_bf16(v); }
+  static __device__ __forceinline__ real ldb(rsrc_t r, int voff, int soff) {
+    return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+  }
+  static __device__ __forceinline__ void stb(real v, rsrc_t r, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16(v), r, voff, soff, 0);
+  }
+  static __device__ __forceinline__ void ldb2(rsrc_t r, int voff, int soff, real& lo, real& hi) {
+    const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    lo = bf16_to_f32(uint16_t(v & 0xffffu));
+    hi = bf16_to_f32(uint16_t(v >> 16));
+  }
 };
 template <> struct StoreT<ST_F16> {
   using elem = _Float16; using real = float;
   static constexpr bool dev = true, stores_dev = true, kahan = true;
   static __device__ __forceinline__ real ld(const elem* p) { return float(*p); }
   static __device__ __forceinline__ void st(elem* p, real v) { *p = _Float16(v); }
+  static __device__ __forceinline__ real ldb(rsrc_t r, int voff, int soff) {
+    return float(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
+  }
+  static __device__ __forceinline__ void stb(real v, rsrc_t r, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, _Float16(v)), r, voff, soff, 0);
+  }
+  static __device__ __forceinline__ void ldb2(rsrc_t r, int voff, int soff, real& lo, real& hi) {
+    const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+    lo = float(__builtin_bit_cast(_Float16, uint16_t(v & 0xffffu)));
+    hi = float(__builtin_bit_cast(_Float16, uint16_t(v >> 16)));
+  }
 };
 
 // ---------------------------------------------------------------------------
@@ -131,12 +191,17 @@ struct KParams {
   double cmom1;        // 1 / sum_i w_i xh_ix^2 - 1 with the FP32-rounded constants
 };
 
-// Cells per thread along the register (outer) axis.
-template <int D, int Q, int A, int RBYTES, int MODE>
+// Cells per thread along the register (outer) axis: every cell keeps its
+// A * Q interpolated values in registers until the collision.
+template <int D, int Q, int A, int ST, int MODE>
 constexpr int cells_per_thread() {
-  constexpr int vals = A * Q * (RBYTES / 4) * ((MODE == MODE_ADJ_STEP || MODE == MODE_ADJ_COLLIDE) ? 2 : 1);
+  constexpr int rb = (ST == ST_F64) ? 8 : 4;
+  constexpr int vals = A * Q * (rb / 4) * ((MODE == MODE_ADJ_STEP || MODE == MODE_ADJ_COLLIDE) ? 2 : 1);
   if (D == 2) return vals <= 40 ? 4 : (vals <= 80 ? 2 : 1);
-  return vals <= 30 ? 4 : (vals <= 90 ? 2 : 1);
+  // 16-bit storage halves the bytes per value: its kernels keep two cells per
+  // thread (fewer halo re-reads) at lower occupancy
+  if (ST == ST_BF16 || ST == ST_F16) return vals <= 30 ? 4 : (vals <= 90 ? 2 : 1);
+  return vals <= 30 ? 4 : (vals <= 60 ? 2 : 1);
 }
 
 // Node index on the grid: periodic wrap (valid for i in [-n, 2n)) or, on an
@@ -162,7 +227,7 @@ struct Tile {
   static constexpr int TX = 64;
   static constexpr int NW = 4;                       // waves per block
   static constexpr int H = NS - 1;
-  static constexpr int PX = TX + H;                  // widest LDS row
+  static constexpr int PX = TX + ((H + 2) & ~1);     // widest LDS row (even: pairs of x)
   static constexpr int PM = (D == 3) ? NW + H : NW;  // rows per outer plane in P
   static constexpr int TOUT = (D == 3) ? RO : NW * RO;  // outer extent of the tile
   static constexpr int PSZ = A * RO * PM * PX;       // one P buffer
@@ -201,6 +266,18 @@ __device__ __forceinline__ E* at(E* base, int e) {
   return reinterpret_cast<E*>(reinterpret_cast<char*>(base) + uint32_t(e) * uint32_t(sizeof(E)));
 }
 
+// First population whose velocity component along `axis` equals q's.  The
+// stencil offset and weights along an axis depend on that component only, so
+// indexing the tables by this representative lets the compiler share the
+// offsets, weights and column addresses between populations.
+template <int SET, int axis>
+constexpr int axis_rep(int q) {
+  using S = Set<SET>;
+  for (int k = 0; k < q; ++k)
+    if (S::xh(k, axis) == S::xh(q, axis)) return k;
+  return q;
+}
+
 // Shape of population q's work: which axes move (and so need n taps and a
 // halo), how many source columns phase A covers, and in how many rounds of
 // 256 threads.
@@ -215,10 +292,17 @@ struct PopShape {
   static constexpr bool direct = !mx && !mm;  // no LDS: each thread loads its own column
   static constexpr int HX = mx ? NS - 1 : 0, HM = mm ? NS - 1 : 0, HO = mo ? NS - 1 : 0;
   static constexpr int KX = mx ? NS : 1, KM = mm ? NS : 1, KO = mo ? NS : 1;
-  static constexpr int CX = TL::TX + HX;
+  // 3D populations through LDS load x in pairs of adjacent nodes (one
+  // two-element load per pair; the window starts at an even node, so it may
+  // begin one node early: sh below)
+  static constexpr bool X2 = D == 3 && !direct;
+  static constexpr int CXL = TL::TX + HX;  // x columns the y and x passes use
+  static constexpr int CX = X2 ? (mx ? (TL::TX + HX + 2) / 2 : TL::TX / 2) : CXL;  // load columns (pairs if X2)
+  static constexpr int XW = X2 ? 2 : 1;   // x nodes per load column
   static constexpr int CM = (D == 3) ? TL::NW + HM : TL::NW;
   static constexpr int NCOL = CX * CM;
   static constexpr int ROUNDS = direct ? 1 : (NCOL + 255) / 256;
+  static_assert(!X2 || 2 * CX <= TL::PX, "LDS row too short for the pair window");
 };
 
 // Everything population q needs after its loads were issued: the loaded
@@ -228,9 +312,9 @@ template <int SET, int NS, int A, int ST, int RO, int q>
 struct PopIn {
   using PS = PopShape<SET, NS, A, ST, RO, q>;
   using R = typename StoreT<ST>::real;
-  R v[PS::ROUNDS][A][RO + PS::HO];
-  R wx[PS::KX], wm[PS::KM], wo[PS::KO];
+  R v[PS::ROUNDS][A][RO + PS::HO][PS::XW];
   int slot[PS::ROUNDS];
+  int sh;  // X2: the window starts sh (0 or 1) nodes before the stencil's first node
 };
 
 // Issue the HBM loads of population q (all A arrays) of `src` with stencil
@@ -253,23 +337,22 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
   constexpr int HX = PS::HX, HM = PS::HM, HO = PS::HO;
   constexpr int axm = 1, axo = D - 1;
 
+  // x and y offsets through the axis representatives: populations with the
+  // same (x, y) components then share their per-lane column addresses
+  constexpr int qx = axis_rep<SET, 0>(q), qm = axis_rep<SET, axm>(q);
   const cptr<int> offc = as_const(off);
-  const cptr<R> wc = as_const(wts);
-  const int ox = offc[3 * q + 0];
-  const int om = (D == 3) ? offc[3 * q + axm] : 0;
+  const int ox = offc[3 * qx + 0];
+  const int om = (D == 3) ? offc[3 * qm + axm] : 0;
   const int oo = offc[3 * q + axo];
-#pragma unroll
-  for (int k = 0; k < PS::KX; ++k) in.wx[k] = PS::mx ? wc[(3 * q + 0) * NS + k] : R(1);
-#pragma unroll
-  for (int k = 0; k < PS::KM; ++k) in.wm[k] = PS::mm ? wc[(3 * q + axm) * NS + k] : R(1);
-#pragma unroll
-  for (int k = 0; k < PS::KO; ++k) in.wo[k] = PS::mo ? wc[(3 * q + axo) * NS + k] : R(1);
 
   const E* base[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) base[a] = src + int64_t(a * Q + q) * pstride;
 
   int col[PS::ROUNDS], ob[PS::ROUNDS], vo[PS::ROUNDS];
+  int col2[PS::ROUNDS];   // X2: column of the pair's second node
+  bool pair[PS::ROUNDS];  // X2: the pair is one aligned two-element load
+  in.sh = 0;
   if constexpr (PS::direct) {
     // each thread loads its own column
     col[0] = wrap_idx(g.x0 + min(g.lane, g.vx - 1) + ox, g.nx, g.bcx);
@@ -282,6 +365,31 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
       vo[0] = max(1, min(RO, g.vo - g.w * RO));
     }
     in.slot[0] = 0;
+  } else if constexpr (PS::X2) {
+    // pairs (xa + 2j, xa + 2j + 1) from the even node xa at or below x0 + ox
+    const int xs0 = g.x0 + ox;
+    const int xa = g.x0 + (ox & ~1);
+    in.sh = ox & 1;
+    const int xlim = xs0 + g.vx + HX;  // one node beyond the last one the stencil needs
+    // pairs start at even element offsets: aligned when the array base and the
+    // population stride are (and nx is even, which makes every row even)
+    const bool aligned2 = (g.nx & 1) == 0 && (pstride & 1) == 0 &&
+                          (reinterpret_cast<uintptr_t>(src) % (2 * sizeof(E))) == 0;
+#pragma unroll
+    for (int rr = 0; rr < PS::ROUNDS; ++rr) {
+      const int c = min(g.tid + 256 * rr, PS::NCOL - 1);
+      const int j = c % PS::CX, ms = c / PS::CX;
+      in.slot[rr] = ms * TL::PX + 2 * j;
+      const int e0 = max(min(xa + 2 * j, xlim), -g.nx), e1 = max(min(xa + 2 * j + 1, xlim), -g.nx);
+      col[rr] = wrap_idx(min(e0, 2 * g.nx - 1), g.nx, g.bcx);
+      col2[rr] = wrap_idx(min(e1, 2 * g.nx - 1), g.nx, g.bcx);
+      const int cm = wrap_idx(g.m0 + om + min(ms, g.vm - 1 + HM), g.nm, g.bcm) * g.sm;
+      // one two-element load when the pair is adjacent in memory and aligned;
+      // else two single loads (clamped x boundary, odd nx, unaligned buffer)
+      pair[rr] = aligned2 && col2[rr] == col[rr] + 1;
+      col[rr] += cm;
+      col2[rr] += cm;
+    }
   } else {
 #pragma unroll
     for (int rr = 0; rr < PS::ROUNDS; ++rr) {
@@ -299,14 +407,53 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
       }
     }
   }
+  // 3D: the row is the same for the whole block, so its byte offset goes into
+  // a scalar register and only the column offset is per lane
+  rsrc_t rs[A];
+  if constexpr (D == 3) {
 #pragma unroll
-  for (int rr = 0; rr < PS::ROUNDS; ++rr) {
-    if (PS::direct || PS::NCOL % 256 == 0 || rr + 1 < PS::ROUNDS || g.tid + 256 * rr < PS::NCOL) {
+    for (int a = 0; a < A; ++a) rs[a] = make_rsrc(base[a], pstride);
+  }
+  if constexpr (PS::X2) {
 #pragma unroll
-      for (int r = 0; r < RO + HO; ++r) {
-        const int e = wrap_idx(ob[rr] + oo + min(r, vo[rr] - 1 + HO), g.no, g.bco) * g.so + col[rr];
+    for (int rr = 0; rr < PS::ROUNDS; ++rr) {
+      if (PS::NCOL % 256 == 0 || rr + 1 < PS::ROUNDS || g.tid + 256 * rr < PS::NCOL) {
+        if (pair[rr]) {
 #pragma unroll
-        for (int a = 0; a < A; ++a) in.v[rr][a][r] = TR::ld(at(base[a], e));
+          for (int r = 0; r < RO + HO; ++r) {
+            const int row = wrap_idx(g.o0 + oo + min(r, g.vo - 1 + HO), g.no, g.bco) * g.so;
+#pragma unroll
+            for (int a = 0; a < A; ++a)
+              TR::ldb2(rs[a], col[rr] * int(sizeof(E)), row * int(sizeof(E)), in.v[rr][a][r][0], in.v[rr][a][r][1]);
+          }
+        } else {
+#pragma unroll
+          for (int r = 0; r < RO + HO; ++r) {
+            const int row = wrap_idx(g.o0 + oo + min(r, g.vo - 1 + HO), g.no, g.bco) * g.so;
+#pragma unroll
+            for (int a = 0; a < A; ++a) {
+              in.v[rr][a][r][0] = TR::ldb(rs[a], col[rr] * int(sizeof(E)), row * int(sizeof(E)));
+              in.v[rr][a][r][1] = TR::ldb(rs[a], col2[rr] * int(sizeof(E)), row * int(sizeof(E)));
+            }
+          }
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int rr = 0; rr < PS::ROUNDS; ++rr) {
+      if (PS::direct || PS::NCOL % 256 == 0 || rr + 1 < PS::ROUNDS || g.tid + 256 * rr < PS::NCOL) {
+#pragma unroll
+        for (int r = 0; r < RO + HO; ++r) {
+          const int row = wrap_idx(ob[rr] + oo + min(r, vo[rr] - 1 + HO), g.no, g.bco) * g.so;
+#pragma unroll
+          for (int a = 0; a < A; ++a) {
+            if constexpr (D == 3)
+              in.v[rr][a][r][0] = TR::ldb(rs[a], col[rr] * int(sizeof(E)), row * int(sizeof(E)));
+            else
+              in.v[rr][a][r][0] = TR::ld(at(base[a], row + col[rr]));
+          }
+        }
       }
     }
   }
@@ -316,102 +463,205 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
 #pragma unroll
       for (int a = 0; a < A; ++a)
 #pragma unroll
-        for (int r = 0; r < RO + HO; ++r) in.v[rr][a][r] -= ref[a];
+        for (int r = 0; r < RO + HO; ++r)
+#pragma unroll
+          for (int k = 0; k < PS::XW; ++k) in.v[rr][a][r][k] -= ref[a];
   }
 }
 
-// Interpolate the loaded population q into out[a][r]: along the outer axis
-// in registers, then (LDS populations) along y and x through the LDS buffers
-// P and T of the current parity.
+// Stencil weights of population q along x, y and the outer axis (scalar
+// loads, read when the population is interpolated rather than with its HBM
+// loads, so that they do not hold scalar registers while the loads are in
+// flight).
 template <int SET, int NS, int A, int ST, int RO, int q>
-__device__ __forceinline__ void pop_finish(const Geo& g, PopIn<SET, NS, A, ST, RO, q>& in,
-                                           typename StoreT<ST>::real* P, typename StoreT<ST>::real* T,
-                                           typename StoreT<ST>::real (&out)[A][RO]) {
+struct PopW {
+  using PS = PopShape<SET, NS, A, ST, RO, q>;
+  using R = typename StoreT<ST>::real;
+  R wx[PS::KX], wm[PS::KM], wo[PS::KO];
+  __device__ __forceinline__ explicit PopW(const R* __restrict__ wts) {
+    constexpr int axm = 1, axo = PS::D - 1;
+    const cptr<R> wc = as_const(wts);
+#pragma unroll
+    for (int k = 0; k < PS::KX; ++k) wx[k] = PS::mx ? wc[(3 * q + 0) * NS + k] : R(1);
+#pragma unroll
+    for (int k = 0; k < PS::KM; ++k) wm[k] = PS::mm ? wc[(3 * q + axm) * NS + k] : R(1);
+#pragma unroll
+    for (int k = 0; k < PS::KO; ++k) wo[k] = PS::mo ? wc[(3 * q + axo) * NS + k] : R(1);
+  }
+};
+
+// The interpolation of a loaded population runs in three stages:
+//   A  outer-axis interpolation in registers; the result goes to LDS buffer P
+//      (populations moving along x or y) or straight to out (the others);
+//   B  y interpolation P -> T in LDS (populations moving along y, 3D);
+//   C  x interpolation from P or T into out.
+// A block barrier separates A from B and B from C.
+template <int SET, int NS, int A, int ST, int RO, int q>
+__device__ __forceinline__ void stage_A(const Geo& g, PopIn<SET, NS, A, ST, RO, q>& in,
+                                        const PopW<SET, NS, A, ST, RO, q>& w, typename StoreT<ST>::real* P,
+                                        typename StoreT<ST>::real (&out)[A][RO]) {
   using PS = PopShape<SET, NS, A, ST, RO, q>;
   using TL = typename PS::TL;
   using R = typename StoreT<ST>::real;
-  constexpr int KX = PS::KX, KM = PS::KM, KO = PS::KO, HM = PS::HM;
+  constexpr int KO = PS::KO;
   constexpr int PX = TL::PX, PM = TL::PM;
-
-  auto outer = [&](const R (&v)[A][RO + PS::HO], R (&res)[A][RO]) {
+  constexpr int XW = PS::XW;
+  // outer-axis interpolation of x node k of one load column
+  auto outer = [&](const R (&v)[A][RO + PS::HO][XW], int k, R (&res)[A][RO]) {
 #pragma unroll
     for (int a = 0; a < A; ++a)
 #pragma unroll
       for (int r = 0; r < RO; ++r) {
         if constexpr (KO == 1) {
-          res[a][r] = v[a][r];
+          res[a][r] = v[a][r][k];
         } else {
-          R s = v[a][r] * in.wo[0];
+          R s = v[a][r][k] * w.wo[0];
 #pragma unroll
-          for (int k = 1; k < KO; ++k) s = fma(in.wo[k], v[a][r + k], s);
+          for (int t = 1; t < KO; ++t) s = fma(w.wo[t], v[a][r + t][k], s);
           res[a][r] = s;
         }
       }
   };
-
   if constexpr (PS::direct) {
-    outer(in.v[0], out);
+    outer(in.v[0], 0, out);
   } else {
-    // ---- phase A (second half): outer interpolation -> LDS
 #pragma unroll
     for (int rr = 0; rr < PS::ROUNDS; ++rr) {
       if (PS::NCOL % 256 == 0 || rr + 1 < PS::ROUNDS || g.tid + 256 * rr < PS::NCOL) {
-        R res[A][RO];
-        outer(in.v[rr], res);
 #pragma unroll
-        for (int a = 0; a < A; ++a)
+        for (int k = 0; k < XW; ++k) {
+          R res[A][RO];
+          outer(in.v[rr], k, res);
 #pragma unroll
-          for (int r = 0; r < RO; ++r) P[(a * RO + r) * PM * PX + in.slot[rr]] = res[a][r];
-      }
-    }
-    __syncthreads();
-    const R* X = P;  // rows the x pass reads: [a][r][row][x], row = wave
-    if constexpr (PS::mm) {
-      // ---- phase B: y interpolation in LDS, one thread per (a, r, x) column
-      constexpr int NB = A * RO * PS::CX;
+          for (int a = 0; a < A; ++a)
 #pragma unroll
-      for (int c0 = 0; c0 < NB; c0 += 256) {
-        const int c = c0 + g.tid;
-        if (NB % 256 == 0 || c < NB) {
-          const int xs = c % PS::CX, ar = c / PS::CX;
-          R colv[TL::NW + HM];
-#pragma unroll
-          for (int m = 0; m < TL::NW + HM; ++m) colv[m] = P[(ar * PM + m) * PX + xs];
-#pragma unroll
-          for (int m = 0; m < TL::NW; ++m) {
-            R s = colv[m] * in.wm[0];
-#pragma unroll
-            for (int k = 1; k < KM; ++k) s = fma(in.wm[k], colv[m + k], s);
-            T[(ar * TL::NW + m) * PX + xs] = s;
-          }
+            for (int r = 0; r < RO; ++r) P[(a * RO + r) * PM * PX + in.slot[rr] + k] = res[a][r];
         }
       }
-      __syncthreads();
-      X = T;
     }
-    // ---- phase C: x interpolation from LDS into registers
+  }
+}
+
+// y interpolation in LDS, one thread per (a, r, x) column
+template <int SET, int NS, int A, int ST, int RO, int q>
+__device__ __forceinline__ void stage_B(const Geo& g, const PopW<SET, NS, A, ST, RO, q>& w, int sh,
+                                        const typename StoreT<ST>::real* P, typename StoreT<ST>::real* T) {
+  using PS = PopShape<SET, NS, A, ST, RO, q>;
+  using TL = typename PS::TL;
+  using R = typename StoreT<ST>::real;
+  constexpr int KM = PS::KM, HM = PS::HM;
+  constexpr int PX = TL::PX, PM = TL::PM;
+  if constexpr (PS::mm) {
+    constexpr int NB = A * RO * PS::CXL;
+#pragma unroll
+    for (int c0 = 0; c0 < NB; c0 += 256) {
+      const int c = c0 + g.tid;
+      if (NB % 256 == 0 || c < NB) {
+        const int xs = c % PS::CXL, ar = c / PS::CXL;
+        R colv[TL::NW + HM];
+#pragma unroll
+        for (int m = 0; m < TL::NW + HM; ++m) colv[m] = P[(ar * PM + m) * PX + xs + sh];
+#pragma unroll
+        for (int m = 0; m < TL::NW; ++m) {
+          R s = colv[m] * w.wm[0];
+#pragma unroll
+          for (int k = 1; k < KM; ++k) s = fma(w.wm[k], colv[m + k], s);
+          T[(ar * TL::NW + m) * PX + xs] = s;
+        }
+      }
+    }
+  }
+}
+
+// x interpolation from LDS into registers (populations that use LDS)
+template <int SET, int NS, int A, int ST, int RO, int q>
+__device__ __forceinline__ void stage_C(const Geo& g, const PopW<SET, NS, A, ST, RO, q>& w, int sh,
+                                        const typename StoreT<ST>::real* P, const typename StoreT<ST>::real* T,
+                                        typename StoreT<ST>::real (&out)[A][RO]) {
+  using PS = PopShape<SET, NS, A, ST, RO, q>;
+  using TL = typename PS::TL;
+  using R = typename StoreT<ST>::real;
+  constexpr int KX = PS::KX;
+  constexpr int PX = TL::PX, PM = TL::PM;
+  if constexpr (!PS::direct) {
+    const R* X = PS::mm ? T : P;              // rows [a][r][row][x], row = wave
     constexpr int XR = PS::mm ? TL::NW : PM;  // rows per (a, r) plane of X
 #pragma unroll
     for (int a = 0; a < A; ++a)
 #pragma unroll
       for (int r = 0; r < RO; ++r) {
-        const R* row = X + ((a * RO + r) * XR + g.w) * PX + g.lane;
+        const R* row = X + ((a * RO + r) * XR + g.w) * PX + g.lane + (PS::mm ? 0 : sh);
         if constexpr (KX == 1) {
           out[a][r] = row[0];
         } else {
-          R s = row[0] * in.wx[0];
+          R s = row[0] * w.wx[0];
 #pragma unroll
-          for (int k = 1; k < KX; ++k) s = fma(in.wx[k], row[k], s);
+          for (int k = 1; k < KX; ++k) s = fma(w.wx[k], row[k], s);
           out[a][r] = s;
         }
       }
   }
-  // Finish the interpolation here: without this the compiler sinks the last
-  // pass to the collision and keeps every population's n raw taps alive.
+}
+
+// Finish the interpolation where it is written: without this the compiler
+// sinks the last pass to the collision and keeps every population's raw taps
+// alive.
+template <int A, int RO, typename R>
+__device__ __forceinline__ void pin(R (&out)[A][RO]) {
 #pragma unroll
   for (int a = 0; a < A; ++a)
 #pragma unroll
     for (int r = 0; r < RO; ++r) asm volatile("" : "+v"(out[a][r]));
+}
+
+// Interpolate the loaded population q into out[a][r] using LDS buffers P, T.
+template <int SET, int NS, int A, int ST, int RO, int q>
+__device__ __forceinline__ void pop_finish(const Geo& g, PopIn<SET, NS, A, ST, RO, q>& in,
+                                           const typename StoreT<ST>::real* __restrict__ wts,
+                                           typename StoreT<ST>::real* P, typename StoreT<ST>::real* T,
+                                           typename StoreT<ST>::real (&out)[A][RO]) {
+  using PS = PopShape<SET, NS, A, ST, RO, q>;
+  const PopW<SET, NS, A, ST, RO, q> w(wts);
+  stage_A(g, in, w, P, out);
+  if constexpr (!PS::direct) {
+    __syncthreads();
+    if constexpr (PS::mm) {
+      stage_B(g, w, in.sh, P, T);
+      __syncthreads();
+    }
+    stage_C(g, w, in.sh, P, T, out);
+  }
+  pin(out);
+}
+
+// Two populations through the same barriers: twice the independent work
+// between block synchronizations and half the synchronizations.
+template <int SET, int NS, int A, int ST, int RO, int q0, int q1>
+__device__ __forceinline__ void pair_finish(const Geo& g, PopIn<SET, NS, A, ST, RO, q0>& in0,
+                                            PopIn<SET, NS, A, ST, RO, q1>& in1,
+                                            const typename StoreT<ST>::real* __restrict__ wts,
+                                            typename StoreT<ST>::real* P0, typename StoreT<ST>::real* P1,
+                                            typename StoreT<ST>::real* T0, typename StoreT<ST>::real* T1,
+                                            typename StoreT<ST>::real (&out0)[A][RO],
+                                            typename StoreT<ST>::real (&out1)[A][RO]) {
+  using PS0 = PopShape<SET, NS, A, ST, RO, q0>;
+  using PS1 = PopShape<SET, NS, A, ST, RO, q1>;
+  const PopW<SET, NS, A, ST, RO, q0> w0(wts);
+  const PopW<SET, NS, A, ST, RO, q1> w1(wts);
+  stage_A(g, in0, w0, P0, out0);
+  stage_A(g, in1, w1, P1, out1);
+  if constexpr (!PS0::direct || !PS1::direct) {
+    __syncthreads();
+    if constexpr (PS0::mm || PS1::mm) {
+      stage_B(g, w0, in0.sh, P0, T0);
+      stage_B(g, w1, in1.sh, P1, T1);
+      __syncthreads();
+    }
+    stage_C(g, w0, in0.sh, P0, T0, out0);
+    stage_C(g, w1, in1.sh, P1, T1, out1);
+  }
+  pin(out0);
+  pin(out1);
 }
 
 // Whether population q uses LDS (needs the block-wide passes).
@@ -428,52 +678,166 @@ constexpr int lds_rank() {  // number of LDS-using populations before q
   return c;
 }
 
-// Software pipeline over the populations: the HBM loads of population q + 1
-// are issued before population q is interpolated, so their latency overlaps
-// with q's LDS passes and barriers.  `sink(q, out)` receives each result.
-template <int SET, int NS, int A, int ST, int RO, bool SUB, int PARITY>
+// Software pipeline over the populations.  GROUP 1: the HBM loads of
+// population q + DEPTH are issued before population q is interpolated, so
+// their latency overlaps with DEPTH populations' LDS passes and barriers.
+// GROUP 2: the rest population first, then the others in pairs that share
+// their barriers; the loads of the next pair are issued before a pair is
+// interpolated.  LDS: Pb holds NPBUF buffers of Tile::PSZ, Tb two of
+// Tile::TSZ; consecutive users of LDS alternate between buffers so that a
+// population's stage A never overwrites what a lagging wave still reads.
+// `sink(q, out)` receives each result.
+template <int SET, int NS, int A, int ST, int RO, bool SUB, int PARITY, int DEPTH = 1, int GROUP = 1>
 struct Pipe {
   using R = typename StoreT<ST>::real;
   using E = typename StoreT<ST>::elem;
+  using TL = Tile<SET, NS, A, ST, RO>;
   static constexpr int Q = Set<SET>::Q;
+  static constexpr int NPBUF = 2 * GROUP;
 
   static __device__ __forceinline__ void refs(int q, R cv2, R (&ref)[A]) {
     ref[0] = SUB ? R(Set<SET>::T.w[q]) : R(0);
     if constexpr (A == 2) ref[1] = SUB ? cv2 * R(Set<SET>::T.w[q]) : R(0);
   }
 
+  template <int q>
+  static __device__ __forceinline__ void load(const Geo& g, const E* __restrict__ src, int64_t pstride,
+                                              const int* __restrict__ off, const R* __restrict__ wts, R cv2,
+                                              PopIn<SET, NS, A, ST, RO, q>& in) {
+    R ref[A];
+    refs(q, cv2, ref);
+    pop_load<SET, NS, A, ST, RO, q, SUB>(g, src, pstride, off, wts, ref, in);
+  }
+
+  template <int q, class Sink>
+  static __device__ __forceinline__ void finish(const Geo& g, const R* __restrict__ wts, R* Pb, R* Tb,
+                                                PopIn<SET, NS, A, ST, RO, q>& cur, Sink&& sink) {
+    constexpr int buf = (lds_rank<SET, NS, q>() + PARITY) & 1;
+    R o[A][RO];
+    pop_finish<SET, NS, A, ST, RO, q>(g, cur, wts, Pb + buf * TL::PSZ, Tb + buf * TL::TSZ, o);
+    sink(std::integral_constant<int, q>{}, o);
+  }
+
+  // one population in flight ahead: cur (q) is loaded on entry
   template <int q, class Sink>
   static __device__ __forceinline__ void run(const Geo& g, const E* __restrict__ src, int64_t pstride,
                                              const int* __restrict__ off, const R* __restrict__ wts, R cv2,
-                                             R* P0, R* P1, R* T0, R* T1, PopIn<SET, NS, A, ST, RO, q>& cur,
-                                             Sink&& sink) {
-    constexpr int buf = (lds_rank<SET, NS, q>() + PARITY) & 1;
-    R o[A][RO];
+                                             R* Pb, R* Tb, PopIn<SET, NS, A, ST, RO, q>& cur, Sink&& sink) {
     if constexpr (q + 1 < Q) {
       PopIn<SET, NS, A, ST, RO, q + 1> nxt;
-      R ref[A];
-      refs(q + 1, cv2, ref);
-      pop_load<SET, NS, A, ST, RO, q + 1, SUB>(g, src, pstride, off, wts, ref, nxt);
-      pop_finish<SET, NS, A, ST, RO, q>(g, cur, buf ? P1 : P0, buf ? T1 : T0, o);
-      sink(std::integral_constant<int, q>{}, o);
-      run<q + 1>(g, src, pstride, off, wts, cv2, P0, P1, T0, T1, nxt, sink);
+      load<q + 1>(g, src, pstride, off, wts, cv2, nxt);
+      finish<q>(g, wts, Pb, Tb, cur, sink);
+      run<q + 1>(g, src, pstride, off, wts, cv2, Pb, Tb, nxt, sink);
     } else {
-      pop_finish<SET, NS, A, ST, RO, q>(g, cur, buf ? P1 : P0, buf ? T1 : T0, o);
-      sink(std::integral_constant<int, q>{}, o);
+      finish<q>(g, wts, Pb, Tb, cur, sink);
+    }
+  }
+
+  // two in flight: cur (q) and nxt (q + 1) are loaded on entry
+  template <int q, class Sink>
+  static __device__ __forceinline__ void run2(const Geo& g, const E* __restrict__ src, int64_t pstride,
+                                              const int* __restrict__ off, const R* __restrict__ wts, R cv2,
+                                              R* Pb, R* Tb, PopIn<SET, NS, A, ST, RO, q>& cur,
+                                              PopIn<SET, NS, A, ST, RO, q + 1>& nxt, Sink&& sink) {
+    if constexpr (q + 2 < Q) {
+      PopIn<SET, NS, A, ST, RO, q + 2> n2;
+      load<q + 2>(g, src, pstride, off, wts, cv2, n2);
+      finish<q>(g, wts, Pb, Tb, cur, sink);
+      run2<q + 1>(g, src, pstride, off, wts, cv2, Pb, Tb, nxt, n2, sink);
+    } else {
+      finish<q>(g, wts, Pb, Tb, cur, sink);
+      run<q + 1>(g, src, pstride, off, wts, cv2, Pb, Tb, nxt, sink);  // the last population
+    }
+  }
+
+  // three in flight: cur (q), n1 (q + 1) and n2 (q + 2) are loaded on entry
+  template <int q, class Sink>
+  static __device__ __forceinline__ void run3(const Geo& g, const E* __restrict__ src, int64_t pstride,
+                                              const int* __restrict__ off, const R* __restrict__ wts, R cv2,
+                                              R* Pb, R* Tb, PopIn<SET, NS, A, ST, RO, q>& cur,
+                                              PopIn<SET, NS, A, ST, RO, q + 1>& n1,
+                                              PopIn<SET, NS, A, ST, RO, q + 2>& n2, Sink&& sink) {
+    if constexpr (q + 3 < Q) {
+      PopIn<SET, NS, A, ST, RO, q + 3> n3;
+      load<q + 3>(g, src, pstride, off, wts, cv2, n3);
+      finish<q>(g, wts, Pb, Tb, cur, sink);
+      run3<q + 1>(g, src, pstride, off, wts, cv2, Pb, Tb, n1, n2, n3, sink);
+    } else {
+      finish<q>(g, wts, Pb, Tb, cur, sink);
+      run2<q + 1>(g, src, pstride, off, wts, cv2, Pb, Tb, n1, n2, sink);  // the last two
+    }
+  }
+
+  // pairs: c0 (q) and c1 (q + 1) are loaded on entry; pair k = (q - 1) / 2
+  template <int q, class Sink>
+  static __device__ __forceinline__ void run_pairs(const Geo& g, const E* __restrict__ src, int64_t pstride,
+                                                   const int* __restrict__ off, const R* __restrict__ wts, R cv2,
+                                                   R* Pb, R* Tb, PopIn<SET, NS, A, ST, RO, q>& c0,
+                                                   PopIn<SET, NS, A, ST, RO, q + 1>& c1, Sink&& sink) {
+    constexpr int slot = ((((q - 1) / 2) + PARITY) & 1) * 2;
+    R o0[A][RO], o1[A][RO];
+    auto fin = [&]() {
+      pair_finish<SET, NS, A, ST, RO, q, q + 1>(g, c0, c1, wts, Pb + slot * TL::PSZ, Pb + (slot + 1) * TL::PSZ,
+                                                Tb, Tb + TL::TSZ, o0, o1);
+      sink(std::integral_constant<int, q>{}, o0);
+      sink(std::integral_constant<int, q + 1>{}, o1);
+    };
+    if constexpr (q + 3 < Q) {
+      PopIn<SET, NS, A, ST, RO, q + 2> n0;
+      PopIn<SET, NS, A, ST, RO, q + 3> n1;
+      load<q + 2>(g, src, pstride, off, wts, cv2, n0);
+      load<q + 3>(g, src, pstride, off, wts, cv2, n1);
+      fin();
+      run_pairs<q + 2>(g, src, pstride, off, wts, cv2, Pb, Tb, n0, n1, sink);
+    } else {
+      fin();
     }
   }
 
   template <class Sink>
   static __device__ __forceinline__ void all(const Geo& g, const E* __restrict__ src, int64_t pstride,
                                              const int* __restrict__ off, const R* __restrict__ wts, R cv2,
-                                             R* P0, R* P1, R* T0, R* T1, Sink&& sink) {
+                                             R* Pb, R* Tb, Sink&& sink) {
     PopIn<SET, NS, A, ST, RO, 0> first;
-    R ref[A];
-    refs(0, cv2, ref);
-    pop_load<SET, NS, A, ST, RO, 0, SUB>(g, src, pstride, off, wts, ref, first);
-    run<0>(g, src, pstride, off, wts, cv2, P0, P1, T0, T1, first, sink);
+    load<0>(g, src, pstride, off, wts, cv2, first);
+    if constexpr (GROUP == 2) {
+      static_assert(Q % 2 == 1 && !uses_lds<SET, NS, 0>(), "pairs need the rest population first");
+      PopIn<SET, NS, A, ST, RO, 1> p1;
+      PopIn<SET, NS, A, ST, RO, 2> p2;
+      load<1>(g, src, pstride, off, wts, cv2, p1);
+      load<2>(g, src, pstride, off, wts, cv2, p2);
+      finish<0>(g, wts, Pb, Tb, first, sink);
+      run_pairs<1>(g, src, pstride, off, wts, cv2, Pb, Tb, p1, p2, sink);
+    } else if constexpr (DEPTH == 3 && Q >= 3) {
+      PopIn<SET, NS, A, ST, RO, 1> second;
+      PopIn<SET, NS, A, ST, RO, 2> third;
+      load<1>(g, src, pstride, off, wts, cv2, second);
+      load<2>(g, src, pstride, off, wts, cv2, third);
+      run3<0>(g, src, pstride, off, wts, cv2, Pb, Tb, first, second, third, sink);
+    } else if constexpr (DEPTH == 2 && Q >= 2) {
+      PopIn<SET, NS, A, ST, RO, 1> second;
+      load<1>(g, src, pstride, off, wts, cv2, second);
+      run2<0>(g, src, pstride, off, wts, cv2, Pb, Tb, first, second, sink);
+    } else {
+      run<0>(g, src, pstride, off, wts, cv2, Pb, Tb, first, sink);
+    }
+  }
+
+  // parity the next pipeline over the same LDS buffers must start with
+  static constexpr int next_parity() {
+    return GROUP == 2 ? (((Q - 1) / 2 + PARITY) & 1) : ((lds_rank<SET, NS, Q>() + PARITY) & 1);
   }
 };
+
+// Populations in flight / grouped in the pipeline of the forward pass.
+template <int D, int A, int MODE>
+constexpr int pipe_depth() {
+  return (D == 3 && A == 1 && MODE == MODE_STEP) ? 3 : 1;
+}
+template <int D, int A, int ST, int MODE>
+constexpr int pipe_group() {
+  return (D == 3 && A == 1 && MODE == MODE_STEP) ? 2 : 1;
+}
 
 // ---------------------------------------------------------------------------
 // Equilibrium polynomial P(a, U, eta, X) = f^eq / (w rho), minus 1
@@ -484,7 +848,7 @@ struct Pipe {
 template <int N, int D, bool COMP, typename R>
 __device__ __forceinline__ R peq_minus1(R a, R U, R eta, R X) {
   R a2 = a * a;
-  R s = a + R(0.5) * (a2 - U);
+  R s = fma(a, fma(R(0.5), a, R(1)), R(-0.5) * U);  // a + (a^2 - U) / 2
   if constexpr (COMP) s += R(0.5) * eta * (X - R(D));
   if constexpr (N >= 3) {
     R t = a * (a2 - R(3) * U);
@@ -546,11 +910,12 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
   constexpr int Q = S::Q;
   constexpr bool DEV = TR::dev;
   constexpr bool COMP = (A == 2);
-  constexpr int RO = cells_per_thread<D, Q, A, int(sizeof(R)), MODE>();
+  constexpr int RO = cells_per_thread<D, Q, A, ST, MODE>();
   using TL = Tile<SET, NS, A, ST, RO>;
 
-  __shared__ R P_lds[2][TL::PSZ];
-  __shared__ R T_lds[2][TL::TSZ];
+  constexpr int DEPTH = pipe_depth<D, A, MODE>(), GROUP = pipe_group<D, A, ST, MODE>();
+  __shared__ __align__(16) R P_lds[2 * GROUP][TL::PSZ];
+  __shared__ __align__(16) R T_lds[2][TL::TSZ];
 
   Geo g;
   g.tid = threadIdx.x;
@@ -602,8 +967,8 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
   const R cv2 = R(p.cv2mD);
 
   if constexpr (MODE != MODE_ADJ_STREAM) {
-    Pipe<SET, NS, A, ST, RO, SUBREF, 0>::all(g, src, p.pstride, p.off, wts, cv2, P_lds[0], P_lds[1], T_lds[0],
-                                               T_lds[1], [&](auto qc, R (&o)[A][RO]) {
+    Pipe<SET, NS, A, ST, RO, SUBREF, 0, DEPTH, GROUP>::all(g, src, p.pstride, p.off, wts, cv2, &P_lds[0][0],
+                                                            &T_lds[0][0], [&](auto qc, R (&o)[A][RO]) {
       constexpr int q = decltype(qc)::value;
 #pragma unroll
       for (int a = 0; a < A; ++a)
@@ -614,9 +979,11 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
   if constexpr (MODE == MODE_ADJ_STEP || MODE == MODE_ADJ_STREAM) {
     // S^T applied to src2 with the transposed stencil; src2 is of the compute type
     const E* __restrict__ src2 = static_cast<const E*>(p.src2);
-    constexpr int parity = (MODE == MODE_ADJ_STREAM) ? 0 : (lds_rank<SET, NS, Q>() & 1);
-    Pipe<SET, NS, 1, ST, RO, false, parity>::all(g, src2, p.pstride, p.off_t, wts_t, cv2, P_lds[0], P_lds[1],
-                                                  T_lds[0], T_lds[1], [&](auto qc, R (&o)[1][RO]) {
+    constexpr int parity =
+        (MODE == MODE_ADJ_STREAM) ? 0 : Pipe<SET, NS, A, ST, RO, SUBREF, 0, DEPTH, GROUP>::next_parity();
+    static_assert(MODE == MODE_ADJ_STREAM || A == 1, "adjoint kernels are built for one array");
+    Pipe<SET, NS, 1, ST, RO, false, parity>::all(g, src2, p.pstride, p.off_t, wts_t, cv2, &P_lds[0][0],
+                                                  &T_lds[0][0], [&](auto qc, R (&o)[1][RO]) {
       constexpr int q = decltype(qc)::value;
 #pragma unroll
       for (int r = 0; r < RO; ++r) {
@@ -641,18 +1008,28 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
   E* __restrict__ dst = static_cast<E*>(p.dst);
   const E* __restrict__ lam_in = static_cast<const E*>(p.src2);
 
-#pragma unroll
-  for (int r = 0; r < RO; ++r) {
-    if (r >= ovalid) break;
-    const int64_t cell = (D == 3) ? (int64_t(obase + r) * g.nm + mi) * g.nx + xi : int64_t(obase + r) * g.nx + xi;
+  // 3D: the row (obase + r) is uniform, so its byte offset goes into a scalar
+  // register and each lane adds its offset within the row.  Rows past the
+  // domain (a partial z tile) get an offset beyond the buffer, where the
+  // hardware drops the store.
+  auto lc_of = [&](int r) -> int { return (D == 3) ? mi * g.nx + xi : (obase + r) * g.nx + xi; };
+  auto rowb_of = [&](int r) -> int {
+    return (D == 3) ? (r < ovalid ? (obase + r) * g.so * int(sizeof(E)) : int(0x80000000u)) : 0;
+  };
+  auto put_at = [&](int k, int r, R v) {  // store array k (population, or Q + population) of cell r
+    if constexpr (D == 3)
+      TR::stb(v, make_rsrc(dst + int64_t(k) * p.pstride, p.pstride), lc_of(r) * int(sizeof(E)), rowb_of(r));
+    else
+      TR::st(at(dst + int64_t(k) * p.pstride, lc_of(r)), v);
+  };
 
-    if constexpr (MODE == MODE_ADJ_STREAM) {
-      static_for<Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        TR::st(dst + int64_t(q) * p.pstride + cell, ft[q][r]);
-      });
-    } else {
-
+  // ---- moments of cell r (Sec. 3): rho, j~ = sum xh f, u~, and for the
+  // compressible model the energy sums, theta and the local relaxation rate
+  struct Mom {
+    R rho, dr, ux, uy, uz, U, theta, eta, omega, Epre;
+    double Epre64;
+  };
+  auto moments = [&](int r) -> Mom {
     // ---- moments (Sec. 3): rho, j~ = sum xh f (and energy sums)
     R rho, jx = R(0), jy = R(0), jz = R(0);
     R Ef = R(0), G = R(0);
@@ -735,6 +1112,13 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
     const R ux = jx * inv_rho, uy = jy * inv_rho, uz = (D == 3) ? jz * inv_rho : R(0);
     const R U = ux * ux + uy * uy + uz * uz;
 
+    Mom m;
+    m.rho = rho;
+    m.dr = rho - R(1);
+    m.ux = ux; m.uy = uy; m.uz = uz; m.U = U;
+    m.Epre = Epre;
+    m.Epre64 = Epre64;
+    m.theta = R(1); m.eta = R(0); m.omega = R(p.omega);
     if constexpr (MODE == MODE_STEP) {
       R omega = R(p.omega), theta = R(1), eta = R(0);
       if constexpr (COMP) {
@@ -756,66 +1140,112 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
         const R tau = R(0.5) + R(p.tau_m_half) / (rho * theta);
         omega = R(1) / tau;
       }
-      // FP32 forms: the set's constants rounded to float give sum_i w_i xh_i xh_i
-      // = (1 + m) I with |m| ~ 1e-8, which BGK with omega near 2 would turn
-      // into a steady drift of the momentum (and in the compressible model of
-      // the energy).  The missing equilibrium momentum rho m' u~ (m' = 1/(1+m) - 1)
-      // is restored as w_i rho m' (xh_i . u~) and the missing energy as w_i dE / sum w,
-      // both added to the small non-equilibrium difference f^eq - f before it is
-      // scaled by omega, where they are far above its rounding.  Neither changes the
-      // other invariants (odd/even symmetry of the set).
-      R kmom = R(0), Eeq = R(0);
-      double Eeq64 = 0.0;
-      if constexpr (DEV) kmom = rho * R(p.cmom1);
-      static_for<Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
+      m.theta = theta; m.eta = eta; m.omega = omega;
+    }
+    (void)Ef; (void)G; (void)Ed;
+    return m;
+  };
+
+  if constexpr (MODE == MODE_STEP) {
+    Mom mc[RO];
+#pragma unroll
+    for (int r = 0; r < RO; ++r) mc[r] = moments(r);
+    // Float compute: the set's constants rounded to float give sum_i w_i xh_i xh_i
+    // = (1 + m) I with |m| ~ 1e-8, which BGK with omega near 2 would turn
+    // into a steady drift of the momentum (and in the compressible model of
+    // the energy).  The missing equilibrium momentum rho m' u~ (m' = 1/(1+m) - 1)
+    // is restored as w_i rho m' (xh_i . u~) and the missing energy as w_i dE / sum w,
+    // both added to the small non-equilibrium difference f^eq - f before it is
+    // scaled by omega, where they are far above its rounding.  Neither changes the
+    // other invariants (odd/even symmetry of the set).
+    // 16-bit storage rounds far above these defects: no energy restoration there.
+    constexpr bool EFIX = COMP && DEV && !TR::kahan;
+    R Eeq[RO];
+    double Eeq64[RO];
+#pragma unroll
+    for (int r = 0; r < RO; ++r) { Eeq[r] = R(0); Eeq64[r] = 0.0; }
+    // populations outer, cells inner: each population's store address is set up once
+    static_for<Q>([&](auto qc) {
+      constexpr int q = decltype(qc)::value;
+      constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
+      const R w = R(S::w(q));
+#pragma unroll
+      for (int r = 0; r < RO; ++r) {
+        if (D == 2 && r >= ovalid) break;
+        const Mom& m = mc[r];
         R a = R(0);
-        if constexpr (S::moves(q, 0)) a = fma(R(S::xh(q, 0)), ux, a);
-        if constexpr (S::moves(q, 1)) a = fma(R(S::xh(q, 1)), uy, a);
-        if constexpr (D == 3 && S::moves(q, 2)) a = fma(R(S::xh(q, 2)), uz, a);
-        const R pm1 = peq_minus1<N, D, COMP, R>(a, U, eta, R(X));
-        const R w = R(S::w(q));
-        R feq_dev;  // f^eq - w (DEV) or f^eq
-        if constexpr (DEV) feq_dev = w * fma(rho - R(1), R(1) + pm1, pm1);
-        else feq_dev = w * rho * (R(1) + pm1);
+        if constexpr (S::moves(q, 0)) a = fma(R(S::xh(q, 0)), m.ux, a);
+        if constexpr (S::moves(q, 1)) a = fma(R(S::xh(q, 1)), m.uy, a);
+        if constexpr (D == 3 && S::moves(q, 2)) a = fma(R(S::xh(q, 2)), m.uz, a);
+        const R pm1 = peq_minus1<N, D, COMP, R>(a, m.U, m.eta, R(X));
+        R feq_dev;  // f^eq - w = w ((rho - 1) + rho (P - 1)) (DEV), or f^eq
+        if constexpr (DEV) feq_dev = fma(w * m.rho, pm1, w * m.dr);
+        else feq_dev = w * m.rho * (R(1) + pm1);
         // f* = f + omega (f^eq - f): the small non-equilibrium part carries the rounding
         R df = feq_dev - ft[q][r];
-        if constexpr (DEV && X != 0.0) df = fma(w * kmom, a, df);
-        const R fo = fma(omega, df, ft[q][r]);
-        TR::st(dst + int64_t(q) * p.pstride + cell, SUBREF ? fo + w : fo);
+        if constexpr (DEV && X != 0.0) df = fma(w * (m.rho * R(p.cmom1)), a, df);
+        const R fo = fma(m.omega, df, ft[q][r]);
+        put_at(q, r, SUBREF ? fo + w : fo);
         if constexpr (COMP) {
           R geq;
-          if constexpr (DEV) geq = cv2 * fma(theta, feq_dev, eta * w);
-          else geq = cv2 * theta * feq_dev;
-          if constexpr (DEV) {
-            if constexpr (X != 0.0) Eeq = fma(R(X), feq_dev, Eeq);
-            Eeq += geq;
-            if (p.e64 != 0.0) Eeq64 += X * double(feq_dev) + double(geq);
+          if constexpr (DEV) geq = cv2 * fma(m.theta, feq_dev, m.eta * w);
+          else geq = cv2 * m.theta * feq_dev;
+          if constexpr (EFIX) {
+            if constexpr (X != 0.0) Eeq[r] = fma(R(X), feq_dev, Eeq[r]);
+            Eeq[r] += geq;
+            if (p.e64 != 0.0) Eeq64[r] += X * double(feq_dev) + double(geq);
             ft[q][r] = geq - ft[Q + q][r];  // f_q is stored: its register keeps g^eq - g
           } else {
-            const R go = fma(omega, geq - ft[Q + q][r], ft[Q + q][r]);
-            TR::st(dst + int64_t(Q + q) * p.pstride + cell, go);
+            const R go = fma(m.omega, geq - ft[Q + q][r], ft[Q + q][r]);
+            put_at(Q + q, r, SUBREF ? go + cv2 * w : go);
           }
         }
+      }
+    });
+    if constexpr (EFIX) {
+      R cE[RO];
+#pragma unroll
+      for (int r = 0; r < RO; ++r) {
+        cE[r] = (mc[r].Epre - Eeq[r]) * R(1.0 / p.sw);
+        if (p.e64 != 0.0) cE[r] = R((mc[r].Epre64 - Eeq64[r]) / p.sw);
+      }
+      static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        const R w = R(S::w(q));
+#pragma unroll
+        for (int r = 0; r < RO; ++r) {
+          if (D == 2 && r >= ovalid) break;
+          const R go = fma(mc[r].omega, fma(w, cE[r], ft[q][r]), ft[Q + q][r]);
+          put_at(Q + q, r, SUBREF ? go + cv2 * w : go);
+        }
       });
-      if constexpr (COMP && DEV) {
-        R cE = (Epre - Eeq) * R(1.0 / p.sw);
-        if (p.e64 != 0.0) cE = R((Epre64 - Eeq64) / p.sw);
+    }
+  } else {
+#pragma unroll
+    for (int r = 0; r < RO; ++r) {
+      if (r >= ovalid) break;
+      auto put = [&](int k, R v) { put_at(k, r, v); };
+      const int lc = lc_of(r), rowb = rowb_of(r);
+      auto get_lam = [&](int k) -> R {
+        if constexpr (D == 3)
+          return TR::ldb(make_rsrc(lam_in + int64_t(k) * p.pstride, p.pstride), lc * int(sizeof(E)), rowb);
+        else
+          return TR::ld(at(lam_in + int64_t(k) * p.pstride, lc));
+      };
+      if constexpr (MODE == MODE_ADJ_STREAM) {
         static_for<Q>([&](auto qc) {
           constexpr int q = decltype(qc)::value;
-          const R w = R(S::w(q));
-          const R go = fma(omega, fma(w, cE, ft[q][r]), ft[Q + q][r]);
-          TR::st(dst + int64_t(Q + q) * p.pstride + cell, SUBREF ? go + cv2 * w : go);
+          put(q, ft[q][r]);
         });
-      }
-    } else {
+      } else {
+        const Mom mm = moments(r);
+        const R ux = mm.ux, uy = mm.uy, uz = mm.uz, U = mm.U;
       // adjoint of the weakly compressible collision at this cell
       R lm[Q];
       if constexpr (MODE == MODE_ADJ_COLLIDE) {
         static_for<Q>([&](auto qc) {
           constexpr int q = decltype(qc)::value;
-          lm[q] = TR::ld(lam_in + int64_t(q) * p.pstride + cell);
+          lm[q] = get_lam(q);
         });
       } else {
         static_for<Q>([&](auto qc) {
@@ -852,10 +1282,10 @@ __global__ __launch_bounds__(256) void sl_kernel(KParams p) {
         if constexpr (S::moves(q, 1)) m = fma(R(S::xh(q, 1)), vy, m);
         if constexpr (D == 3 && S::moves(q, 2)) m = fma(R(S::xh(q, 2)), vz, m);
         const R mu = fma(om1, lm[q], omega * m);
-        TR::st(dst + int64_t(q) * p.pstride + cell, mu);
+        put(q, mu);
       });
+      }
     }
-    }  // not ADJ_STREAM
   }
 }
 
