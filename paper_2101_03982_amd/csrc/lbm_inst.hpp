@@ -21,19 +21,20 @@ hipError_t launch_step(const KParams& p, hipStream_t s) {
   using R = typename StoreT<ST>::real;
   constexpr int D = Set<SET>::D;
   constexpr int RO = cells_per_thread<D, Set<SET>::Q, A, ST, MODE>();
+  using TL = Tile<SET, NS, A, ST, RO>;
   KParams q = p;
-  q.tiles[0] = (p.n[0] + 63) / 64;
+  q.tiles[0] = (p.n[0] + TL::TX - 1) / TL::TX;
   if (D == 3) {
-    q.tiles[1] = (p.n[1] + 3) / 4;
+    q.tiles[1] = (p.n[1] + TL::NW - 1) / TL::NW;
     q.tiles[2] = (p.n[2] + RO - 1) / RO;
   } else {
-    q.tiles[1] = (p.n[1] + 4 * RO - 1) / (4 * RO);
+    q.tiles[1] = (p.n[1] + TL::NW * RO - 1) / (TL::NW * RO);
     q.tiles[2] = 1;
   }
   const int64_t ntiles = int64_t(q.tiles[0]) * q.tiles[1] * q.tiles[2];
   q.chunk = int((ntiles + 7) / 8);
   const dim3 grid(unsigned(q.chunk) * 8u);
-  hipLaunchKernelGGL((sl_kernel<SET, NS, N, A, ST, MODE>), grid, dim3(256), 0, s, q);
+  hipLaunchKernelGGL((sl_kernel<SET, NS, N, A, ST, MODE>), grid, dim3(TL::NT), 0, s, q);
   return hipGetLastError();
 }
 

@@ -197,7 +197,9 @@ template <int D, int Q, int A, int ST, int MODE>
 constexpr int cells_per_thread() {
   constexpr int rb = (ST == ST_F64) ? 8 : 4;
   constexpr int vals = A * Q * (rb / 4) * ((MODE == MODE_ADJ_STEP || MODE == MODE_ADJ_COLLIDE) ? 2 : 1);
-  if (D == 2) return vals <= 40 ? 4 : (vals <= 80 ? 2 : 1);
+  // 2D grids are small (512^2 = 2^18 cells): two cells per thread for the
+  // f + g sets keeps more than two blocks per compute unit
+  if (D == 2) return vals <= 30 ? 4 : (vals <= 80 ? 2 : 1);
   // 16-bit storage halves the bytes per value: its kernels keep two cells per
   // thread (fewer halo re-reads) at lower occupancy
   if (ST == ST_BF16 || ST == ST_F16) return vals <= 30 ? 4 : (vals <= 90 ? 2 : 1);
@@ -225,7 +227,11 @@ struct Tile {
   using E = typename TR::elem;
   static constexpr int D = S::D;
   static constexpr int TX = 64;
-  static constexpr int NW = 4;                       // waves per block
+  // waves per block: eight (a 64x8xRO tile, less y halo per cell) for the
+  // 17-21 velocity sets, where two such blocks still fit on a compute unit
+  // and the measured gain is largest (3 %); four elsewhere
+  static constexpr int NW = (D == 3 && A == 1 && RO == 4 && S::Q > 16 && S::Q <= 21) ? 8 : 4;
+  static constexpr int NT = 64 * NW;                 // threads per block
   static constexpr int H = NS - 1;
   static constexpr int PX = TX + ((H + 2) & ~1);     // widest LDS row (even: pairs of x)
   static constexpr int PM = (D == 3) ? NW + H : NW;  // rows per outer plane in P
@@ -301,7 +307,7 @@ struct PopShape {
   static constexpr int XW = X2 ? 2 : 1;   // x nodes per load column
   static constexpr int CM = (D == 3) ? TL::NW + HM : TL::NW;
   static constexpr int NCOL = CX * CM;
-  static constexpr int ROUNDS = direct ? 1 : (NCOL + 255) / 256;
+  static constexpr int ROUNDS = direct ? 1 : (NCOL + TL::NT - 1) / TL::NT;
   static_assert(!X2 || 2 * CX <= TL::PX, "LDS row too short for the pair window");
 };
 
@@ -377,7 +383,7 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
                           (reinterpret_cast<uintptr_t>(src) % (2 * sizeof(E))) == 0;
 #pragma unroll
     for (int rr = 0; rr < PS::ROUNDS; ++rr) {
-      const int c = min(g.tid + 256 * rr, PS::NCOL - 1);
+      const int c = min(g.tid + TL::NT * rr, PS::NCOL - 1);
       const int j = c % PS::CX, ms = c / PS::CX;
       in.slot[rr] = ms * TL::PX + 2 * j;
       const int e0 = max(min(xa + 2 * j, xlim), -g.nx), e1 = max(min(xa + 2 * j + 1, xlim), -g.nx);
@@ -393,7 +399,7 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
   } else {
 #pragma unroll
     for (int rr = 0; rr < PS::ROUNDS; ++rr) {
-      const int c = min(g.tid + 256 * rr, PS::NCOL - 1);
+      const int c = min(g.tid + TL::NT * rr, PS::NCOL - 1);
       const int xs = c % PS::CX, ms = c / PS::CX;
       in.slot[rr] = ms * TL::PX + xs;
       col[rr] = wrap_idx(g.x0 + ox + min(xs, g.vx - 1 + HX), g.nx, g.bcx);
@@ -417,7 +423,7 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
   if constexpr (PS::X2) {
 #pragma unroll
     for (int rr = 0; rr < PS::ROUNDS; ++rr) {
-      if (PS::NCOL % 256 == 0 || rr + 1 < PS::ROUNDS || g.tid + 256 * rr < PS::NCOL) {
+      if (PS::NCOL % TL::NT == 0 || rr + 1 < PS::ROUNDS || g.tid + TL::NT * rr < PS::NCOL) {
         if (pair[rr]) {
 #pragma unroll
           for (int r = 0; r < RO + HO; ++r) {
@@ -442,7 +448,7 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
   } else {
 #pragma unroll
     for (int rr = 0; rr < PS::ROUNDS; ++rr) {
-      if (PS::direct || PS::NCOL % 256 == 0 || rr + 1 < PS::ROUNDS || g.tid + 256 * rr < PS::NCOL) {
+      if (PS::direct || PS::NCOL % TL::NT == 0 || rr + 1 < PS::ROUNDS || g.tid + TL::NT * rr < PS::NCOL) {
 #pragma unroll
         for (int r = 0; r < RO + HO; ++r) {
           const int row = wrap_idx(ob[rr] + oo + min(r, vo[rr] - 1 + HO), g.no, g.bco) * g.so;
@@ -527,7 +533,7 @@ __device__ __forceinline__ void stage_A(const Geo& g, PopIn<SET, NS, A, ST, RO, 
   } else {
 #pragma unroll
     for (int rr = 0; rr < PS::ROUNDS; ++rr) {
-      if (PS::NCOL % 256 == 0 || rr + 1 < PS::ROUNDS || g.tid + 256 * rr < PS::NCOL) {
+      if (PS::NCOL % TL::NT == 0 || rr + 1 < PS::ROUNDS || g.tid + TL::NT * rr < PS::NCOL) {
 #pragma unroll
         for (int k = 0; k < XW; ++k) {
           R res[A][RO];
@@ -554,9 +560,9 @@ __device__ __forceinline__ void stage_B(const Geo& g, const PopW<SET, NS, A, ST,
   if constexpr (PS::mm) {
     constexpr int NB = A * RO * PS::CXL;
 #pragma unroll
-    for (int c0 = 0; c0 < NB; c0 += 256) {
+    for (int c0 = 0; c0 < NB; c0 += TL::NT) {
       const int c = c0 + g.tid;
-      if (NB % 256 == 0 || c < NB) {
+      if (NB % TL::NT == 0 || c < NB) {
         const int xs = c % PS::CXL, ar = c / PS::CXL;
         R colv[TL::NW + HM];
 #pragma unroll
@@ -900,8 +906,14 @@ struct Kahan {
 // The fused kernel
 // ---------------------------------------------------------------------------
 
+// Threads per block of the fused kernel.
+template <int SET, int NS, int A, int ST, int MODE>
+constexpr int sl_threads() {
+  return Tile<SET, NS, A, ST, cells_per_thread<Set<SET>::D, Set<SET>::Q, A, ST, MODE>()>::NT;
+}
+
 template <int SET, int NS, int N, int A, int ST, int MODE>
-__global__ __launch_bounds__(256) void sl_kernel(KParams p) {
+__global__ __launch_bounds__((sl_threads<SET, NS, A, ST, MODE>())) void sl_kernel(KParams p) {
   using S = Set<SET>;
   using TR = StoreT<ST>;
   using R = typename TR::real;
