@@ -201,7 +201,8 @@ constexpr int cells_per_thread() {
   // f + g sets keeps more than two blocks per compute unit
   if (D == 2) return vals <= 30 ? 4 : (vals <= 80 ? 2 : 1);
   // 16-bit storage halves the bytes per value: its kernels keep two cells per
-  // thread (fewer halo re-reads) at lower occupancy
+  // thread (fewer halo re-reads; measured faster at 256^3 than one cell at
+  // higher occupancy)
   if (ST == ST_BF16 || ST == ST_F16) return vals <= 30 ? 4 : (vals <= 90 ? 2 : 1);
   return vals <= 30 ? 4 : (vals <= 60 ? 2 : 1);
 }
@@ -230,7 +231,10 @@ struct Tile {
   // waves per block: eight (a 64x8xRO tile, less y halo per cell) for the
   // 17-21 velocity sets, where two such blocks still fit on a compute unit
   // and the measured gain is largest (3 %); four elsewhere
-  static constexpr int NW = (D == 3 && A == 1 && RO == 4 && S::Q > 16 && S::Q <= 21) ? 8 : 4;
+  // and for the FP32 f + g kernels with one cell per thread
+  static constexpr int NW =
+      ((D == 3 && A == 1 && RO == 4 && S::Q > 16 && S::Q <= 21) || (D == 3 && A == 2 && RO == 1 && ST == ST_F32))
+          ? 8 : 4;
   static constexpr int NT = 64 * NW;                 // threads per block
   static constexpr int H = NS - 1;
   static constexpr int PX = TX + ((H + 2) & ~1);     // widest LDS row (even: pairs of x)
@@ -685,15 +689,14 @@ constexpr int lds_rank() {  // number of LDS-using populations before q
 }
 
 // Software pipeline over the populations.  GROUP 1: the HBM loads of
-// population q + DEPTH are issued before population q is interpolated, so
-// their latency overlaps with DEPTH populations' LDS passes and barriers.
-// GROUP 2: the rest population first, then the others in pairs that share
-// their barriers; the loads of the next pair are issued before a pair is
-// interpolated.  LDS: Pb holds NPBUF buffers of Tile::PSZ, Tb two of
+// population q + 1 are issued before population q is interpolated, so their
+// latency overlaps with q's LDS passes and barriers.  GROUP 2: the rest
+// population first, then the others in pairs that share their barriers; the
+// loads of the next pair are issued before a pair is interpolated.  LDS: Pb holds NPBUF buffers of Tile::PSZ, Tb two of
 // Tile::TSZ; consecutive users of LDS alternate between buffers so that a
 // population's stage A never overwrites what a lagging wave still reads.
 // `sink(q, out)` receives each result.
-template <int SET, int NS, int A, int ST, int RO, bool SUB, int PARITY, int DEPTH = 1, int GROUP = 1>
+template <int SET, int NS, int A, int ST, int RO, bool SUB, int PARITY, int GROUP = 1>
 struct Pipe {
   using R = typename StoreT<ST>::real;
   using E = typename StoreT<ST>::elem;
@@ -739,41 +742,6 @@ struct Pipe {
     }
   }
 
-  // two in flight: cur (q) and nxt (q + 1) are loaded on entry
-  template <int q, class Sink>
-  static __device__ __forceinline__ void run2(const Geo& g, const E* __restrict__ src, int64_t pstride,
-                                              const int* __restrict__ off, const R* __restrict__ wts, R cv2,
-                                              R* Pb, R* Tb, PopIn<SET, NS, A, ST, RO, q>& cur,
-                                              PopIn<SET, NS, A, ST, RO, q + 1>& nxt, Sink&& sink) {
-    if constexpr (q + 2 < Q) {
-      PopIn<SET, NS, A, ST, RO, q + 2> n2;
-      load<q + 2>(g, src, pstride, off, wts, cv2, n2);
-      finish<q>(g, wts, Pb, Tb, cur, sink);
-      run2<q + 1>(g, src, pstride, off, wts, cv2, Pb, Tb, nxt, n2, sink);
-    } else {
-      finish<q>(g, wts, Pb, Tb, cur, sink);
-      run<q + 1>(g, src, pstride, off, wts, cv2, Pb, Tb, nxt, sink);  // the last population
-    }
-  }
-
-  // three in flight: cur (q), n1 (q + 1) and n2 (q + 2) are loaded on entry
-  template <int q, class Sink>
-  static __device__ __forceinline__ void run3(const Geo& g, const E* __restrict__ src, int64_t pstride,
-                                              const int* __restrict__ off, const R* __restrict__ wts, R cv2,
-                                              R* Pb, R* Tb, PopIn<SET, NS, A, ST, RO, q>& cur,
-                                              PopIn<SET, NS, A, ST, RO, q + 1>& n1,
-                                              PopIn<SET, NS, A, ST, RO, q + 2>& n2, Sink&& sink) {
-    if constexpr (q + 3 < Q) {
-      PopIn<SET, NS, A, ST, RO, q + 3> n3;
-      load<q + 3>(g, src, pstride, off, wts, cv2, n3);
-      finish<q>(g, wts, Pb, Tb, cur, sink);
-      run3<q + 1>(g, src, pstride, off, wts, cv2, Pb, Tb, n1, n2, n3, sink);
-    } else {
-      finish<q>(g, wts, Pb, Tb, cur, sink);
-      run2<q + 1>(g, src, pstride, off, wts, cv2, Pb, Tb, n1, n2, sink);  // the last two
-    }
-  }
-
   // pairs: c0 (q) and c1 (q + 1) are loaded on entry; pair k = (q - 1) / 2
   template <int q, class Sink>
   static __device__ __forceinline__ void run_pairs(const Geo& g, const E* __restrict__ src, int64_t pstride,
@@ -814,16 +782,6 @@ struct Pipe {
       load<2>(g, src, pstride, off, wts, cv2, p2);
       finish<0>(g, wts, Pb, Tb, first, sink);
       run_pairs<1>(g, src, pstride, off, wts, cv2, Pb, Tb, p1, p2, sink);
-    } else if constexpr (DEPTH == 3 && Q >= 3) {
-      PopIn<SET, NS, A, ST, RO, 1> second;
-      PopIn<SET, NS, A, ST, RO, 2> third;
-      load<1>(g, src, pstride, off, wts, cv2, second);
-      load<2>(g, src, pstride, off, wts, cv2, third);
-      run3<0>(g, src, pstride, off, wts, cv2, Pb, Tb, first, second, third, sink);
-    } else if constexpr (DEPTH == 2 && Q >= 2) {
-      PopIn<SET, NS, A, ST, RO, 1> second;
-      load<1>(g, src, pstride, off, wts, cv2, second);
-      run2<0>(g, src, pstride, off, wts, cv2, Pb, Tb, first, second, sink);
     } else {
       run<0>(g, src, pstride, off, wts, cv2, Pb, Tb, first, sink);
     }
@@ -835,11 +793,7 @@ struct Pipe {
   }
 };
 
-// Populations in flight / grouped in the pipeline of the forward pass.
-template <int D, int A, int MODE>
-constexpr int pipe_depth() {
-  return (D == 3 && A == 1 && MODE == MODE_STEP) ? 3 : 1;
-}
+// Populations grouped per pair of barriers in the forward pass.
 template <int D, int A, int ST, int MODE>
 constexpr int pipe_group() {
   return (D == 3 && A == 1 && MODE == MODE_STEP) ? 2 : 1;
@@ -912,8 +866,18 @@ constexpr int sl_threads() {
   return Tile<SET, NS, A, ST, cells_per_thread<Set<SET>::D, Set<SET>::Q, A, ST, MODE>()>::NT;
 }
 
+// Minimum waves per SIMD the register allocation must allow: four for the
+// FP32 f + g kernels (two 8-wave blocks per compute unit; a few spilled
+// registers cost less than the lost occupancy, measured 5-7 %), else no bound.
+template <int SET, int NS, int A, int ST, int MODE>
+constexpr int sl_min_waves() {
+  return (Set<SET>::D == 3 && A == 2 && ST == ST_F32 && MODE == MODE_STEP &&
+          cells_per_thread<Set<SET>::D, Set<SET>::Q, A, ST, MODE>() == 1) ? 4 : 1;
+}
+
 template <int SET, int NS, int N, int A, int ST, int MODE>
-__global__ __launch_bounds__((sl_threads<SET, NS, A, ST, MODE>())) void sl_kernel(KParams p) {
+__global__ __launch_bounds__((sl_threads<SET, NS, A, ST, MODE>()), (sl_min_waves<SET, NS, A, ST, MODE>()))
+void sl_kernel(KParams p) {
   using S = Set<SET>;
   using TR = StoreT<ST>;
   using R = typename TR::real;
@@ -925,7 +889,7 @@ __global__ __launch_bounds__((sl_threads<SET, NS, A, ST, MODE>())) void sl_kerne
   constexpr int RO = cells_per_thread<D, Q, A, ST, MODE>();
   using TL = Tile<SET, NS, A, ST, RO>;
 
-  constexpr int DEPTH = pipe_depth<D, A, MODE>(), GROUP = pipe_group<D, A, ST, MODE>();
+  constexpr int GROUP = pipe_group<D, A, ST, MODE>();
   __shared__ __align__(16) R P_lds[2 * GROUP][TL::PSZ];
   __shared__ __align__(16) R T_lds[2][TL::TSZ];
 
@@ -979,7 +943,7 @@ __global__ __launch_bounds__((sl_threads<SET, NS, A, ST, MODE>())) void sl_kerne
   const R cv2 = R(p.cv2mD);
 
   if constexpr (MODE != MODE_ADJ_STREAM) {
-    Pipe<SET, NS, A, ST, RO, SUBREF, 0, DEPTH, GROUP>::all(g, src, p.pstride, p.off, wts, cv2, &P_lds[0][0],
+    Pipe<SET, NS, A, ST, RO, SUBREF, 0, GROUP>::all(g, src, p.pstride, p.off, wts, cv2, &P_lds[0][0],
                                                             &T_lds[0][0], [&](auto qc, R (&o)[A][RO]) {
       constexpr int q = decltype(qc)::value;
 #pragma unroll
@@ -992,7 +956,7 @@ __global__ __launch_bounds__((sl_threads<SET, NS, A, ST, MODE>())) void sl_kerne
     // S^T applied to src2 with the transposed stencil; src2 is of the compute type
     const E* __restrict__ src2 = static_cast<const E*>(p.src2);
     constexpr int parity =
-        (MODE == MODE_ADJ_STREAM) ? 0 : Pipe<SET, NS, A, ST, RO, SUBREF, 0, DEPTH, GROUP>::next_parity();
+        (MODE == MODE_ADJ_STREAM) ? 0 : Pipe<SET, NS, A, ST, RO, SUBREF, 0, GROUP>::next_parity();
     static_assert(MODE == MODE_ADJ_STREAM || A == 1, "adjoint kernels are built for one array");
     Pipe<SET, NS, 1, ST, RO, false, parity>::all(g, src2, p.pstride, p.off_t, wts_t, cv2, &P_lds[0][0],
                                                   &T_lds[0][0], [&](auto qc, R (&o)[1][RO]) {
