@@ -121,9 +121,11 @@ void lbm_default_options(lbm_options *opt);
  * Computes the per-direction stencil (offsets and Lagrange weights) on the
  * host in FP64 and uploads it; allocates small device scratch for reductions.
  * The grid must hold the stencil: along every periodic axis of N nodes
- * every first-node offset o satisfies -N <= o and o + n <= N + 1.  The context uses the current HIP
- * device.  On failure *out is NULL.  Ownership: the caller destroys the
- * context with lbm_destroy(). */
+ * every first-node offset o satisfies -N <= o and o + n <= N + 1.  Size
+ * limits (LBM_EINVAL): fewer than 2^31 cells, and one population plus one
+ * xy plane below 4 GiB (kernels use 32-bit byte offsets within a
+ * population).  The context uses the current HIP device.  On failure *out is
+ * NULL.  Ownership: the caller destroys the context with lbm_destroy(). */
 int lbm_create(lbm_ctx **out, int32_t set, const int64_t grid[3], double tau, int32_t order,
                const lbm_options *opt);
 

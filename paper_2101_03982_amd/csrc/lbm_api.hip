@@ -410,7 +410,11 @@ int lbm_create(lbm_ctx** out, int32_t set, const int64_t grid[3], double tau, in
     c->bc[a] = (a < c->D) ? o.boundary[a] : LBM_PERIODIC;
   }
   c->stream = static_cast<hipStream_t>(o.stream);
-  if ((size_t(c->ncell) * c->elem) >= (size_t(1) << 32)) return bad(LBM_EINVAL, "one population exceeds 4 GiB");
+  // kernels address one population with 32-bit byte offsets, and a partial
+  // tile's dropped stores sit one population beyond its start plus at most
+  // one xy plane
+  if ((size_t(c->ncell) + size_t(grid[0] * grid[1])) * c->elem >= (size_t(1) << 32))
+    return bad(LBM_EINVAL, "one population (plus one xy plane) exceeds 4 GiB");
   c->state_bytes = size_t(c->A) * c->Q * size_t(c->ncell) * c->elem;
 
   // on-lattice: every moving component shifts by a whole number of cells

@@ -61,6 +61,13 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 // scalar register), so that a row offset shared by the block costs no vector
 // instruction.  The resource covers one population array (< 4 GiB).
 using rsrc_t = __amdgpu_buffer_rsrc_t;
+
+// Byte offset of element e for a buffer access, in unsigned 32-bit arithmetic
+// (the host keeps every population, plus one xy plane, below 4 GiB).
+template <class E>
+__device__ __forceinline__ int boff(int e) {
+  return int(uint32_t(e) * uint32_t(sizeof(E)));
+}
 template <class E>
 __device__ __forceinline__ rsrc_t make_rsrc(const E* base, int64_t nelem) {
   // word 3 = 0x00020000: raw (unformatted) 32-bit buffer on gfx9
@@ -434,7 +441,7 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
             const int row = wrap_idx(g.o0 + oo + min(r, g.vo - 1 + HO), g.no, g.bco) * g.so;
 #pragma unroll
             for (int a = 0; a < A; ++a)
-              TR::ldb2(rs[a], col[rr] * int(sizeof(E)), row * int(sizeof(E)), in.v[rr][a][r][0], in.v[rr][a][r][1]);
+              TR::ldb2(rs[a], boff<E>(col[rr]), boff<E>(row), in.v[rr][a][r][0], in.v[rr][a][r][1]);
           }
         } else {
 #pragma unroll
@@ -442,8 +449,8 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
             const int row = wrap_idx(g.o0 + oo + min(r, g.vo - 1 + HO), g.no, g.bco) * g.so;
 #pragma unroll
             for (int a = 0; a < A; ++a) {
-              in.v[rr][a][r][0] = TR::ldb(rs[a], col[rr] * int(sizeof(E)), row * int(sizeof(E)));
-              in.v[rr][a][r][1] = TR::ldb(rs[a], col2[rr] * int(sizeof(E)), row * int(sizeof(E)));
+              in.v[rr][a][r][0] = TR::ldb(rs[a], boff<E>(col[rr]), boff<E>(row));
+              in.v[rr][a][r][1] = TR::ldb(rs[a], boff<E>(col2[rr]), boff<E>(row));
             }
           }
         }
@@ -459,7 +466,7 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
 #pragma unroll
           for (int a = 0; a < A; ++a) {
             if constexpr (D == 3)
-              in.v[rr][a][r][0] = TR::ldb(rs[a], col[rr] * int(sizeof(E)), row * int(sizeof(E)));
+              in.v[rr][a][r][0] = TR::ldb(rs[a], boff<E>(col[rr]), boff<E>(row));
             else
               in.v[rr][a][r][0] = TR::ld(at(base[a], row + col[rr]));
           }
@@ -990,11 +997,13 @@ void sl_kernel(KParams p) {
   // hardware drops the store.
   auto lc_of = [&](int r) -> int { return (D == 3) ? mi * g.nx + xi : (obase + r) * g.nx + xi; };
   auto rowb_of = [&](int r) -> int {
-    return (D == 3) ? (r < ovalid ? (obase + r) * g.so * int(sizeof(E)) : int(0x80000000u)) : 0;
+    // one population's byte size: at or beyond the buffer's end, and with the
+    // lane offset (less than one plane) still below 2^32
+    return (D == 3) ? (r < ovalid ? boff<E>((obase + r) * g.so) : boff<E>(int(p.pstride))) : 0;
   };
   auto put_at = [&](int k, int r, R v) {  // store array k (population, or Q + population) of cell r
     if constexpr (D == 3)
-      TR::stb(v, make_rsrc(dst + int64_t(k) * p.pstride, p.pstride), lc_of(r) * int(sizeof(E)), rowb_of(r));
+      TR::stb(v, make_rsrc(dst + int64_t(k) * p.pstride, p.pstride), boff<E>(lc_of(r)), rowb_of(r));
     else
       TR::st(at(dst + int64_t(k) * p.pstride, lc_of(r)), v);
   };
@@ -1204,7 +1213,7 @@ void sl_kernel(KParams p) {
       const int lc = lc_of(r), rowb = rowb_of(r);
       auto get_lam = [&](int k) -> R {
         if constexpr (D == 3)
-          return TR::ldb(make_rsrc(lam_in + int64_t(k) * p.pstride, p.pstride), lc * int(sizeof(E)), rowb);
+          return TR::ldb(make_rsrc(lam_in + int64_t(k) * p.pstride, p.pstride), boff<E>(lc), rowb);
         else
           return TR::ld(at(lam_in + int64_t(k) * p.pstride, lc));
       };

@@ -111,3 +111,40 @@ def test_compressible_fp32_parity_ragged(orc, Ma):
     lat.step(3)
     f = orc.run(cfg, f, 3)
     assert rel_err(gpu_populations(lat), f) <= 1e-5
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_ctgv_full_size_sampled(orc, storage):
+    """The precision-form workload at its full size (D3Q45 f + g, 256^3,
+    Ma 1.0, the launch configuration the benchmark times): one step from the
+    initial condition at 48 sampled cells against the oracle computed cell
+    by cell.  FP32 within 1e-5 of the largest population; BF16 within three
+    of its ulps of each population's deviation from its reference value."""
+    from paper_2101_03982_amd import Lattice
+
+    from gpu_helpers import to_dev
+
+    wl = W.ctgv_workload(n=256, Ma=1.0)
+    lat = Lattice("D3Q45", wl.grid, wl.tau, 4, stencil=wl.stencil, storage=storage, dx=wl.dx, dt=wl.dt, cs=wl.cs,
+                  compressible=True, gamma=wl.gamma, energy_f64=(storage == "bf16"), device="cuda:0")
+    cfg = orc.Config("D3Q45", wl.grid, tau=wl.tau, order=4, stencil=wl.stencil, dx=wl.dx, dt=wl.dt, cs=wl.cs,
+                     compressible=True, gamma=wl.gamma)
+    rho, u, theta = W.ctgv_fields(wl)
+    lat.init_equilibrium(to_dev(rho, torch.float32), to_dev(u, torch.float32), to_dev(theta, torch.float32))
+    lat.step(1)
+    cells = np.random.default_rng(12).choice(wl.ncell, size=48, replace=False)
+    cells[:3] = [0, wl.ncell - 1, 256 * 256 * 128 + 64]
+    ref = orc.first_step_at(cfg, rho, u, cells, theta=theta)
+    w = np.array(lat.table()["w"])
+    Cv = 1.0 / (wl.gamma - 1.0)
+    r = np.concatenate([w, (2 * Cv - 3) * w])
+    idx = torch.from_numpy(cells).cuda()
+    got = lat.state().reshape(2 * lat.Q, -1)[:, idx].double().cpu().numpy().T + r
+    del lat
+    torch.cuda.empty_cache()
+    if storage == "f32":
+        assert rel_err(got, ref) <= 1e-5, rel_err(got, ref)
+    else:
+        scale = np.max(np.abs(ref - r), axis=0, keepdims=True)
+        tol = 3 * ULP[storage] * scale + 2.0 ** -23
+        assert np.all(np.abs(got - ref) <= tol), float(np.max(np.abs(got - ref) / tol))

@@ -128,6 +128,8 @@ def _create(L, set_id, grid, tau=0.8, order=2, **opt):
     ((3, (8, 8, 8), 0.8, 2, {"compressible": 1}), -4),      # compressible needs N = 4
     ((7, (8, 8, 8), 0.8, 4, {"compressible": 1, "gamma": 1.0}), -1),
     ((5, (8, 8, 8), 0.8, 2, {"boundary": (0, 2, 0)}), -1),
+    ((5, (1024, 1024, 1024), 0.8, 2, {"storage": 1}), -1),  # one FP32 population = 4 GiB
+    ((5, (2048, 2048, 1024), 0.8, 2), -1),                   # 2^32 cells
 ])
 def test_create_rejects(L, args, code):
     set_id, grid = args[0], args[1]
