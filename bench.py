@@ -290,6 +290,37 @@ def large_grid(sets=("D3Q13", "D3Q27"), n=256):
     return out
 
 
+def on_lattice_ratio(n=128):
+    """Context for the paper's cost statement (Sec. 5: semi-Lagrangian
+    streaming costs about ten times on-lattice streaming): D3Q27 FP32 at n^3
+    with integer shifts (streaming is a plain shift) against the tricubic
+    off-lattice step of the Taylor-Green workload, single-launch times."""
+    import math
+
+    import torch
+
+    import lbm_inputs as W
+    from paper_2101_03982_amd import Lattice
+
+    out = {}
+    wl = W.tgv3d_workload("D3Q27", n=n)
+    rho, u, _ = W.tgv3d_fields(wl)
+    cases = {"on_lattice": dict(dx=1.0, dt=1.0, cs=1.0 / math.sqrt(3.0), tau=0.6),
+             "semi_lagrangian": dict(dx=wl.dx, dt=wl.dt, cs=wl.cs, tau=wl.tau)}
+    for name, c in cases.items():
+        lat = Lattice("D3Q27", wl.grid, c["tau"], 2, stencil=4, storage="f32", dx=c["dx"], dt=c["dt"], cs=c["cs"],
+                      device="cuda:0")
+        lat.init_equilibrium(torch.from_numpy(rho).to("cuda:0", torch.float32),
+                             torch.from_numpy(u * (c["cs"] / wl.cs)).to("cuda:0", torch.float32))
+        out[name + "_ms"] = kernel_time(lat)
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    out["ratio"] = out["semi_lagrangian_ms"] / out["on_lattice_ms"]
+    out["workload"] = "D3Q27 %d^3 FP32: integer shifts (1-node copy) vs n = 4 Lagrange streaming" % n
+    return out
+
+
 def svi_throughput(n=512):
     """Shock-vortex workload (D2Q19 / D2Q25, f + g, N = 4, n = 5, extrapolating
     in x) at its full 512^2 size: single-launch time per set and storage."""
@@ -438,6 +469,7 @@ def main():
         out["adjoint"] = adjoint_cost()
         out["large_grid"] = large_grid()
         out["svi"] = svi_throughput()
+        out["on_lattice"] = on_lattice_ratio()
         torch.cuda.empty_cache()
         out["precision"] = precision_form(a.precision_n, a.precision_steps)
     if not a.no_cpu:

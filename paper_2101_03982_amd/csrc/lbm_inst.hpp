@@ -33,6 +33,12 @@ hipError_t launch_step(const KParams& p, hipStream_t s) {
   }
   const int64_t ntiles = int64_t(q.tiles[0]) * q.tiles[1] * q.tiles[2];
   q.chunk = int((ntiles + 7) / 8);
+  q.rsy = q.rsz = 0;
+  if (D == 3) {  // one (y, z) block of tiles per XCD, 2 x 4
+    q.rsy = (q.tiles[1] + 1) / 2;
+    q.rsz = (q.tiles[2] + 3) / 4;
+    q.chunk = q.tiles[0] * q.rsy * q.rsz;
+  }
   const dim3 grid(unsigned(q.chunk) * 8u);
   hipLaunchKernelGGL((sl_kernel<SET, NS, N, A, ST, MODE>), grid, dim3(TL::NT), 0, s, q);
   return hipGetLastError();

@@ -187,6 +187,7 @@ struct KParams {
   int64_t pstride;     // cells per population
   int tiles[3];        // tiles along x, y (3D) / outer (2D), z (3D)
   int chunk;           // tiles per XCD: consecutive logical tiles share an L2
+  int rsy, rsz;        // 3D: y and z tiles of each XCD's block of the grid (0: linear order)
   double omega;        // 1 / tau (weakly compressible)
   double tau_m_half;   // tau_ref - 1/2 (compressible)
   double cv2mD;        // 2 C_v - D
@@ -906,15 +907,27 @@ void sl_kernel(KParams p) {
   g.w = threadIdx.x >> 6;
   g.nx = p.n[0];
   g.bcx = p.bc[0];
-  // XCD-aware tile order: hardware blocks go round-robin to the 8 XCDs; give
-  // each XCD a contiguous run of logical tiles so that the halo rows shared by
-  // neighbouring tiles are read through the same L2.
+  // XCD-aware tile order: hardware blocks go round-robin to the 8 XCDs.  Each
+  // XCD gets one block of the grid (3D: a 2 x 4 split of the y and z tiles,
+  // so that the halo planes two XCDs both read are few), walked x, y, z, so
+  // that the halo rows shared by neighbouring tiles are read through its L2.
   const int bid = blockIdx.x;
-  const int tile = (bid & 7) * p.chunk + (bid >> 3);
-  if (tile >= p.tiles[0] * p.tiles[1] * p.tiles[2]) return;
-  const int tix = tile % p.tiles[0];
-  const int tiy = (tile / p.tiles[0]) % p.tiles[1];
-  const int tiz = tile / (p.tiles[0] * p.tiles[1]);
+  const int xcd = bid & 7, lt = bid >> 3;
+  int tix, tiy, tiz;
+  if (p.rsy > 0) {
+    tix = lt % p.tiles[0];
+    const int rest = lt / p.tiles[0];
+    const int ly = rest % p.rsy, lz = rest / p.rsy;
+    tiy = (xcd & 1) * p.rsy + ly;
+    tiz = (xcd >> 1) * p.rsz + lz;
+    if (lz >= p.rsz || tiy >= p.tiles[1] || tiz >= p.tiles[2]) return;
+  } else {
+    const int tile = xcd * p.chunk + lt;
+    if (tile >= p.tiles[0] * p.tiles[1] * p.tiles[2]) return;
+    tix = tile % p.tiles[0];
+    tiy = (tile / p.tiles[0]) % p.tiles[1];
+    tiz = tile / (p.tiles[0] * p.tiles[1]);
+  }
   g.x0 = tix * TL::TX;
   g.vx = min(TL::TX, g.nx - g.x0);
   if constexpr (D == 3) {
