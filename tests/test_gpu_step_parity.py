@@ -72,16 +72,20 @@ def test_zero_steps_is_a_no_op(orc):
     assert np.array_equal(before.cpu().numpy(), lat.state().cpu().numpy())
 
 
-def test_minimal_grid(orc):
-    """The smallest periodic grid the stencil allows, one tile, all tails."""
-    got, ref = None, None
-    name = "D3Q27"
-    lat, cfg = pair(orc, name, (6, 6, 6), tau=0.7, n=4, storage="f64", dt=0.3, cs=1.0)
-    rho, u, _ = W.random_fields(3, cfg.shape, 4, 0.1)
-    f0 = init_both(lat, orc, cfg, rho, u)
+@pytest.mark.parametrize("name,storage,comp", [("D3Q27", "f64", False), ("D3Q21", "f32", False),
+                                               ("D3Q45", "f32", True)])
+def test_minimal_grid(orc, name, storage, comp):
+    """The smallest periodic grid the stencil allows: one tile, every axis a
+    tail (also for the eight-wave blocks of D3Q21 and the FP32 f + g model)."""
+    cs = 0.6
+    dt = 0.3 / (W.MAX_COMPONENT_OVER_CS[name] * cs)
+    lat, cfg = pair(orc, name, (6, 6, 6), tau=0.7, order=4 if comp else 2, n=4, storage=storage, dt=dt, cs=cs,
+                    compressible=comp)
+    rho, u, theta = W.random_fields(3, cfg.shape, 4, 0.1 * cs, theta_amp=0.05 if comp else 0.0)
+    f0 = init_both(lat, orc, cfg, rho, u, theta)
     lat.step(2)
     got, ref = gpu_populations(lat), orc.run(cfg, f0, 2)
-    assert rel_err(got, ref) <= 1e-12
+    assert rel_err(got, ref) <= TOL[storage] * (3 if comp else 1)
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
