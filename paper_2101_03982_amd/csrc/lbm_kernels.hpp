@@ -7,20 +7,23 @@
 // of the moment and equilibrium arithmetic, and an axis along which a
 // population does not move costs neither a halo nor an interpolation pass.
 //
-// Work decomposition (3D).  A 256-thread block owns a 64 x 4 x RO tile of
-// cells: lane = x, wave = y, and each thread holds RO cells along z.  For each
-// population (unrolled at compile time) the block
-//   A. loads, per (x, y) column of the population's source region (the tile
-//      shifted by the stencil's first-node offset, widened by n - 1 along every
-//      moving axis), the RO + n - 1 values along z from HBM, interpolates along
-//      z in registers and writes RO values per column to LDS;
+// Work decomposition (3D).  A block of NW waves (4; 8 for some sets) owns a
+// 64 x NW x RO tile of cells: lane = x, wave = y, and each thread holds RO
+// cells along z.  For each population (unrolled at compile time) the block
+//   A. loads, per column of the population's source region (the tile shifted
+//      by the stencil's first-node offset, widened by n - 1 along every moving
+//      axis; x in pairs of adjacent nodes), the RO + n - 1 values along z,
+//      interpolates along z in registers and writes RO values per column to
+//      LDS;
 //   B. interpolates along y in LDS (one thread per (z, x) column);
 //   C. interpolates along x from LDS into the thread's registers.
-// A population that moves along z only never touches LDS.  After the last
+// A population that moves along z only never touches LDS.  The HBM loads of
+// the next populations are issued before the current ones are interpolated;
+// in 3D two populations share each pair of block barriers.  After the last
 // population each thread holds all interpolated populations of its RO cells,
 // forms the moments, the Hermite equilibrium in its scalar closed form and
 // the BGK update in registers, and stores coalesced along x.
-// 2D: the same with y in the role of z and the four waves splitting y.
+// 2D: the same with y in the role of z and the waves splitting y.
 //
 // The stencil (first-node offsets and Lagrange weights per population and
 // axis) is computed on the host and read through uniform (scalar) loads.
@@ -55,7 +58,7 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 // dev: the kernels compute on deviations d = f - r from the reference values
 //      r_i = w_i (f) and (2 C_v - D) w_i (g), which keeps rounding relative to
 //      the small deviations instead of the populations;
-// stores_dev: the buffer itself holds deviations (16-bit storage);
+// stores_dev: the buffer itself holds deviations (all but FP64);
 // kahan: moment sums with compensated summation.
 // ldb/stb: buffer accesses at byte offset voff (per lane) + soff (uniform,
 // scalar register), so that a row offset shared by the block costs no vector
@@ -186,7 +189,7 @@ struct KParams {
   int bc[3];           // 0 periodic, 1 extrapolate (clamp)
   int64_t pstride;     // cells per population
   int tiles[3];        // tiles along x, y (3D) / outer (2D), z (3D)
-  int chunk;           // tiles per XCD: consecutive logical tiles share an L2
+  int chunk;           // tiles per XCD
   int rsy, rsz;        // 3D: y and z tiles of each XCD's block of the grid (0: linear order)
   double omega;        // 1 / tau (weakly compressible)
   double tau_m_half;   // tau_ref - 1/2 (compressible)
@@ -236,10 +239,10 @@ struct Tile {
   using E = typename TR::elem;
   static constexpr int D = S::D;
   static constexpr int TX = 64;
-  // waves per block: eight (a 64x8xRO tile, less y halo per cell) for the
-  // 17-21 velocity sets, where two such blocks still fit on a compute unit
-  // and the measured gain is largest (3 %); four elsewhere
-  // and for the FP32 f + g kernels with one cell per thread
+  // waves per block: eight (a 64x8xRO tile, less y halo per cell) where two
+  // such blocks still fit on a compute unit and measured faster: the 17-21
+  // velocity sets (3 %) and the FP32 f + g kernels with one cell per thread
+  // (5-7 %); four elsewhere
   static constexpr int NW =
       ((D == 3 && A == 1 && RO == 4 && S::Q > 16 && S::Q <= 21) || (D == 3 && A == 2 && RO == 1 && ST == ST_F32))
           ? 8 : 4;
@@ -297,8 +300,8 @@ constexpr int axis_rep(int q) {
 }
 
 // Shape of population q's work: which axes move (and so need n taps and a
-// halo), how many source columns phase A covers, and in how many rounds of
-// 256 threads.
+// halo), how many source columns stage A covers, and in how many rounds of
+// the block's threads.
 template <int SET, int NS, int A, int ST, int RO, int q>
 struct PopShape {
   using TL = Tile<SET, NS, A, ST, RO>;
@@ -324,8 +327,8 @@ struct PopShape {
 };
 
 // Everything population q needs after its loads were issued: the loaded
-// values (still in flight until first use), the stencil weights and where
-// each round's column lands in LDS.
+// values (still in flight until first use) and where each round's column
+// lands in LDS.
 template <int SET, int NS, int A, int ST, int RO, int q>
 struct PopIn {
   using PS = PopShape<SET, NS, A, ST, RO, q>;
