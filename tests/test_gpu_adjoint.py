@@ -76,16 +76,19 @@ def test_adjoint_kernels_vs_oracle(orc, name, order):
     assert rel_err(gu.cpu().numpy(), orc.init_transpose(cfg, rho, u, lam)) < 1e-12
 
 
-def test_rollout_gradient_vs_oracle(orc):
+@pytest.mark.parametrize("steps,every", [(20, 6), (200, 20)])
+def test_rollout_gradient_vs_oracle(orc, steps, every):
+    """The 16^3 copy of the differentiation workload: the full 200 steps with
+    checkpoints every 20 (the workload's own), and a short run whose
+    checkpoint interval does not divide the step count."""
     wl = W.adjoint_workload(n=16, storage="f64")
     lat, cfg = pair(orc, wl.set, wl.grid, wl.tau, wl.order, wl.stencil, "f64", wl.dx, wl.dt, wl.cs)
     rho, u, _ = W.tgv3d_fields(wl, sigma=1e-3, seed=1)
-    steps = 20
     u0 = to_dev(u, torch.float64).requires_grad_(True)
-    K = kinetic_energy_after(u0, to_dev(rho, torch.float64), lat, steps, every=6)
+    K = kinetic_energy_after(u0, to_dev(rho, torch.float64), lat, steps, every=every)
     K.backward()
     loss, g = orc.ke_gradient_u0(cfg, rho, u, steps)
-    assert abs(float(K) / loss - 1) < 1e-12
+    assert abs(float(K.detach()) / loss - 1) < 1e-12
     assert rel_err(u0.grad.cpu().numpy(), g) < 1e-10
 
 
