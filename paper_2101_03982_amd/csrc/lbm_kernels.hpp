@@ -1032,7 +1032,7 @@ void sl_kernel(KParams p) {
   };
   auto moments = [&](int r) -> Mom {
     // ---- moments (Sec. 3): rho, j~ = sum xh f (and energy sums)
-    R rho, jx = R(0), jy = R(0), jz = R(0);
+    R rho, drho = R(0), jx = R(0), jy = R(0), jz = R(0);
     R Ef = R(0), G = R(0);
     double Ed = 0.0;
     // total energy sum(|xh|^2 f + g) before the collision, in the frame the
@@ -1055,6 +1055,7 @@ void sl_kernel(KParams p) {
           kg.add(ft[Q + q][r]);
         }
       });
+      drho = R(p.sw - 1.0) + kr.s;
       rho = R(p.sw) + kr.s;
       jx = R(p.swx[0]) + kx.s;
       jy = R(p.swx[1]) + ky.s;
@@ -1082,6 +1083,7 @@ void sl_kernel(KParams p) {
           sg += ft[Q + q][r];
         }
       });
+      drho = R(p.sw - 1.0) + sr;
       rho = R(p.sw) + sr;
       jx += R(p.swx[0]);
       jy += R(p.swx[1]);
@@ -1109,13 +1111,28 @@ void sl_kernel(KParams p) {
         }
       });
     }
-    const R inv_rho = R(1) / rho;
-    const R ux = jx * inv_rho, uy = jy * inv_rho, uz = (D == 3) ? jz * inv_rho : R(0);
+    R ux, uy, uz;
+    if constexpr (DEV) {
+      // u~ = j~ + j~ (1/rho - 1) with 1/rho - 1 = -drho/rho: one rounding on
+      // j~'s own bits.  Rounding 1/rho itself is biased for rho within a few
+      // ulps of 1 (the reciprocal of a float just below 1 falls on or next to
+      // a midpoint of the coarser grid above 1), a bias of ~1e-9 in u~ that BGK
+      // with omega near 2 turns into a steady growth of the kinetic energy.
+      const R im1 = -drho / rho;
+      ux = fma(jx, im1, jx);
+      uy = fma(jy, im1, jy);
+      uz = (D == 3) ? fma(jz, im1, jz) : R(0);
+    } else {
+      const R inv_rho = R(1) / rho;
+      ux = jx * inv_rho;
+      uy = jy * inv_rho;
+      uz = (D == 3) ? jz * inv_rho : R(0);
+    }
     const R U = ux * ux + uy * uy + uz * uz;
 
     Mom m;
     m.rho = rho;
-    m.dr = rho - R(1);
+    m.dr = DEV ? drho : rho - R(1);
     m.ux = ux; m.uy = uy; m.uz = uz; m.U = U;
     m.Epre = Epre;
     m.Epre64 = Epre64;
@@ -1130,11 +1147,11 @@ void sl_kernel(KParams p) {
             theta = R(th);
             eta = R(th - 1.0);
           } else {
-            theta = (Ef - rho * U + G) * R(p.inv2cv) * inv_rho;
+            theta = (Ef - rho * U + G) * R(p.inv2cv) / rho;
             eta = theta - R(1);
           }
         } else {
-          theta = (Ef - rho * U + G) * R(p.inv2cv) * inv_rho;
+          theta = (Ef - rho * U + G) * R(p.inv2cv) / rho;
           eta = theta - R(1);
         }
         // tau = 1/2 + (tau_ref - 1/2) / (rho theta)

@@ -113,3 +113,31 @@ def test_fp32_kinetic_energy_vs_fp64_oracle(orc, name):
     ke_gpu = lat.moments(fields=False)[3].ke
     ke_orc = orc.moments(cfg, f)[3]["ke"]
     assert abs(ke_gpu / ke_orc - 1) <= 1e-5, (ke_gpu, ke_orc)
+
+
+@pytest.mark.parametrize("name", W.TGV3D_SETS)
+def test_fp32_energy_log_full_run(name):
+    """The whole weakly compressible Taylor-Green run (128^3, 2000 steps, the
+    kinetic energy logged every 50 steps): every logged FP32 value within
+    1e-5 of the FP64 run on the GPU, and the dissipation -dK/dt (central
+    differences of the log) within 1e-3 of it."""
+    wl = W.tgv3d_workload(name, n=128)
+    rho, u, _ = W.tgv3d_fields(wl)
+    logs = {}
+    for storage in ("f64", "f32"):
+        lat = Lattice(name, wl.grid, wl.tau, wl.order, stencil=wl.stencil, storage=storage, dx=wl.dx, dt=wl.dt,
+                      cs=wl.cs, device="cuda:0")
+        lat.init_equilibrium(to_dev(rho, lat.dtype), to_dev(u, lat.dtype))
+        ke = [lat.moments(fields=False)[3].ke]
+        for _ in range(2000 // 50):
+            lat.step(50)
+            ke.append(lat.moments(fields=False)[3].ke)
+        logs[storage] = np.array(ke)
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    k32, k64 = logs["f32"], logs["f64"]
+    assert np.max(np.abs(k32 / k64 - 1)) <= 1e-5, np.max(np.abs(k32 / k64 - 1))
+    d32 = -(k32[2:] - k32[:-2]) / (100 * wl.dt)
+    d64 = -(k64[2:] - k64[:-2]) / (100 * wl.dt)
+    assert np.max(np.abs(d32 - d64)) <= 1e-3 * np.max(np.abs(d64))
