@@ -1142,13 +1142,18 @@ void sl_kernel(KParams p) {
       if constexpr (COMP) {
         // 2 rho C_v theta = sum |xh - u~|^2 f + sum g = E_f - rho U + G
         if constexpr (DEV) {
+          // in deviations: 2 C_v rho (theta - 1) = E~ - rho U - 2 C_v (rho - 1),
+          // E~ = sum |xh|^2 (f - w) + sum (g - (2 C_v - D) w), so that theta - 1
+          // is formed from small quantities (no cancellation against 2 C_v)
+          const double twocv = 1.0 / p.inv2cv;
+          const double e0 = p.swX + p.cv2mD * p.sw - twocv;  // zero up to rounding of the table sums
           if (p.e64 != 0.0) {
-            const double th = (Ed - double(rho) * double(U) + double(G)) * p.inv2cv / double(rho);
-            theta = R(th);
-            eta = R(th - 1.0);
+            const double et = (Epre64 + e0 - double(rho) * double(U) - twocv * double(drho)) * p.inv2cv / double(rho);
+            eta = R(et);
+            theta = R(1.0 + et);
           } else {
-            theta = (Ef - rho * U + G) * R(p.inv2cv) / rho;
-            eta = theta - R(1);
+            eta = (Epre + R(e0) - rho * U - R(twocv) * drho) * R(p.inv2cv) / rho;
+            theta = R(1) + eta;
           }
         } else {
           theta = (Ef - rho * U + G) * R(p.inv2cv) / rho;
