@@ -205,15 +205,23 @@ def fd_directions(shape_u, count: int = 16, seed: int = 2):
 # Workload 4: compressible 3D Taylor-Green vortex (CTIC)
 # ---------------------------------------------------------------------------
 
+# Time steps of the paper's D3Q45 runs of the compressible Taylor-Green vortex
+# (Table tab:timestepsizes, Re 400), by Mach number.
+CTGV_PAPER_DT = {0.5: 0.0165, 1.0: 0.0329, 1.5: 0.0178, 2.0: 0.0119}
+
+
 def ctgv_workload(n: int = 256, Ma: float = 0.5, Re: float = 1600.0, steps: int = 1000,
                   storage: str = "f32", set_: str = "D3Q45", stencil: int = 4, gamma: float = 1.4,
-                  courant: float = 0.5) -> Workload:
+                  courant: float = 0.5, dt: float | None = None) -> Workload:
     """Domain [0, 2 pi)^3, u0 = 1, L = 1, rho0 = 1; the sound speed at theta = 1
     is c_s sqrt(gamma) = 1/Ma (Sec. 3: c_s* = c_s sqrt(theta gamma)); mu = 1/Re;
-    N = 4 (Table tab:setup-full3Dvortex); tau quoted at rho theta = 1."""
+    N = 4 (Table tab:setup-full3Dvortex); tau quoted at rho theta = 1.  The
+    time step is the one at the given Courant number of the fastest component,
+    unless ``dt`` is given (e.g. ``CTGV_PAPER_DT[Ma]``)."""
     dx = 2.0 * math.pi / n
     cs = 1.0 / (Ma * math.sqrt(gamma))
-    dt = courant_dt(dx, cs, (set_,), courant)
+    if dt is None:
+        dt = courant_dt(dx, cs, (set_,), courant)
     return Workload("ctgv", set_, (n, n, n), dx, dt, cs, relaxation_time(1.0 / Re, cs, dt), 4, stencil, steps,
                     compressible=True, gamma=gamma, storage=storage)
 
