@@ -42,7 +42,7 @@ def parse():
     ap.add_argument("--log-every", type=int, default=50)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the FP64-error, adjoint-cost, reduced-precision and high-Mach measurements")
+                    help="skip the FP64-error, adjoint-cost, dissipation, reduced-precision and high-Mach measurements")
     ap.add_argument("--precision-n", type=int, default=256)
     ap.add_argument("--precision-steps", type=int, default=1000)
     ap.add_argument("--sets", default=",".join(SETS))
@@ -156,6 +156,56 @@ def adjoint_cost(n=64, steps=200, every=20):
     return {"workload": "D3Q27 %d^3 FP32, %d steps, checkpoints every %d, loss = final kinetic energy" % (
         n, steps, every), "forward_s": fwd, "backward_s": bwd, "plain_forward_s": plain,
         "adjoint_over_forward": bwd / fwd, "adjoint_over_plain_forward": bwd / plain}
+
+
+def dissipation(sets=SETS, n=128, t_end=1.5625, logs=40):
+    """Sec. 4.2's split of the kinetic-energy decay of the weakly compressible
+    Taylor-Green run into the physical dissipation nu E (E = <|curl u|^2>, the
+    library's enstrophy kernel, eighth-order differences) and the rest, the
+    scheme's numerical dissipation: (K(0) - K(t)) / (nu int_0^t E dt) - 1."""
+    import numpy as np
+    import torch
+
+    import lbm_inputs as W
+    from paper_2101_03982_amd import Lattice
+
+    res = {}
+    for s in sets:
+        wl = W.tgv3d_workload(s, n=n)
+        lat = Lattice(s, wl.grid, wl.tau, wl.order, stencil=wl.stencil, storage="f32", dx=wl.dx, dt=wl.dt,
+                      cs=wl.cs, device="cuda:0")
+        rho, u, _ = W.tgv3d_fields(wl)
+        lat.init_equilibrium(torch.from_numpy(rho).to("cuda:0", torch.float32),
+                             torch.from_numpy(u).to("cuda:0", torch.float32))
+        steps = int(round(t_end / wl.dt))
+        every = steps // logs
+        ke, ens, t, ens_ms = [], [], [], []
+        done = 0
+        while True:
+            _, uu, _, d = lat.moments()
+            t0 = time.perf_counter()
+            ens.append(lat.enstrophy(uu))
+            ens_ms.append((time.perf_counter() - t0) * 1e3)
+            ke.append(d.ke)
+            t.append(done * wl.dt)
+            if done >= steps:
+                break
+            k = min(every, steps - done)
+            lat.step(k)
+            done += k
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+        ke, ens, t = np.array(ke), np.array(ens), np.array(t)
+        phys = (1.0 / 1600.0) * np.concatenate([[0.0], np.cumsum(0.5 * (ens[1:] + ens[:-1]) * np.diff(t))])
+        excess = (ke[0] - ke[1:]) / phys[1:] - 1
+        res[s] = {"numerical_over_physical_t%.2f" % t[len(t) // 2]: round(float(excess[len(excess) // 2 - 1]), 4),
+                  "numerical_over_physical_t%.2f" % t[-1]: round(float(excess[-1]), 4),
+                  "enstrophy_t0": round(float(ens[0]), 6), "enstrophy_end": round(float(ens[-1]), 6),
+                  "enstrophy_call_ms": round(float(np.median(ens_ms)), 3)}
+    res["workload"] = "3D Taylor-Green vortex %d^3 FP32, Re 1600, to t = %g, enstrophy every %d steps" % (
+        n, t_end, every)
+    return res
 
 
 def high_mach(n=256, t_end=10.0, machs=(0.5, 1.0, 1.5, 2.0), storage="f32", every=50):
@@ -522,6 +572,7 @@ def main():
         out["large_grid"] = large_grid()
         out["svi"] = svi_throughput()
         out["on_lattice"] = on_lattice_ratio()
+        out["dissipation"] = dissipation(sets)
         torch.cuda.empty_cache()
         out["precision"] = precision_form(a.precision_n, a.precision_steps)
         torch.cuda.empty_cache()

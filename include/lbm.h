@@ -173,6 +173,20 @@ int lbm_step_into(lbm_ctx *ctx, const void *src, void *dst);
  * rho <= 0 or theta <= 0. */
 int lbm_moments(lbm_ctx *ctx, const void *state, void *rho, void *u, void *theta, lbm_diag *diag);
 
+/* Enstrophy E = <|curl u|^2> of a velocity field (Sec. 4.2: the squared
+ * vorticity integrated over the domain and divided by its volume; on the
+ * uniform periodic grid, the mean over the nodes), written to *enstrophy
+ * (host memory).  u is a device array [D][nz][ny][nx] of the compute type in
+ * the units lbm_moments() writes (physical velocity, lengths in units of dx's
+ * length); derivatives are central differences of even order `order`
+ * (2, 4, 6 or 8) with spacing dx, wrapped periodically.  In 2D the vorticity
+ * has only its z component d_x u_y - d_y u_x.  For an incompressible flow
+ * nu E is the physical dissipation rate of the kinetic energy, so its
+ * difference from -dK/dt measures the scheme's numerical dissipation.  FP64
+ * arithmetic.  LBM_EUNSUPPORTED unless every axis is periodic; LBM_EINVAL for
+ * a null pointer or another order.  Synchronizes the context's stream. */
+int lbm_enstrophy(lbm_ctx *ctx, const void *u, int32_t order, double *enstrophy);
+
 /* Waits for the context's stream; reports asynchronous HIP errors. */
 int lbm_sync(lbm_ctx *ctx);
 

@@ -65,6 +65,8 @@ def _stale(src, obj):
     deps = [src] + [os.path.join(CSRC, f) for f in KERNEL_HEADERS]
     if src.endswith("lbm_api.hip"):
         deps.append(os.path.join(HERE, "..", "include", "lbm.h"))
+    if src.endswith("lbm_api.hip") or src.endswith("lbm_diag.hip"):
+        deps.append(os.path.join(CSRC, "lbm_diag.hpp"))
     t = os.path.getmtime(obj)
     return any(os.path.getmtime(d) > t for d in deps if os.path.exists(d))
 
@@ -92,6 +94,7 @@ def build(jobs: int | None = None, verbose: bool = False, force: bool = True) ->
                 fh.write(text)
         units.append((path, os.path.join(BUILD, name + ".o")))
     units.append((os.path.join(CSRC, "lbm_api.hip"), os.path.join(BUILD, "lbm_api.o")))
+    units.append((os.path.join(CSRC, "lbm_diag.hip"), os.path.join(BUILD, "lbm_diag.o")))
     # longest units first (the 3D sets with many combinations)
     units.sort(key=lambda u: ("D3Q45" not in u[0], "D3" not in u[0], u[0]))
     t0 = time.time()

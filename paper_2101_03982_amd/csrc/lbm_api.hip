@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/lbm.h"
+#include "lbm_diag.hpp"
 #include "lbm_dispatch.hpp"
 #include "lbm_sets.hpp"
 
@@ -501,6 +502,31 @@ void* lbm_state(lbm_ctx* c) { return c ? c->buf[c->cur] : nullptr; }
 int lbm_set_stream(lbm_ctx* c, void* stream) {
   if (int r = check_ctx(c)) return r;
   c->stream = static_cast<hipStream_t>(stream);
+  return LBM_OK;
+}
+
+int lbm_enstrophy(lbm_ctx* c, const void* u, int32_t order, double* enstrophy) {
+  if (int r = check_ctx(c)) return r;
+  if (!u || !enstrophy) return fail(LBM_EINVAL, "null pointer");
+  if (order != 2 && order != 4 && order != 6 && order != 8) return fail(LBM_EINVAL, "order must be 2, 4, 6 or 8");
+  for (int a = 0; a < c->D; ++a)
+    if (c->bc[a] != LBM_PERIODIC) return fail(LBM_EUNSUPPORTED, "enstrophy needs periodic axes");
+  if (int r = set_device(c)) return r;
+  // central-difference coefficients of order 2m over the spacing:
+  // c_j = (-1)^(j+1) (m!)^2 / (j (m-j)! (m+j)!) / dx
+  const int m = order / 2;
+  double coef[4];
+  auto fact = [](int k) { double f = 1; for (int i = 2; i <= k; ++i) f *= i; return f; };
+  for (int j = 1; j <= m; ++j)
+    coef[j - 1] = ((j % 2) ? 1.0 : -1.0) * fact(m) * fact(m) / (double(j) * fact(m - j) * fact(m + j)) / c->dx;
+  hipError_t e = launch_enstrophy(u, c->storage == LBM_F64, c->n, c->D, m, coef, c->d_partial,
+                                  MOMENT_BLOCKS * NPART, c->d_result, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "enstrophy kernel");
+  e = hipMemcpyAsync(c->h_result, c->d_result, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  *enstrophy = c->h_result[0] / double(c->ncell);
   return LBM_OK;
 }
 

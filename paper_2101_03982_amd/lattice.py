@@ -178,6 +178,18 @@ class Lattice:
         check(rc, "lbm_moments")
         return rho, u, th, diag
 
+    def enstrophy(self, u=None, order: int = 8) -> float:
+        """<|curl u|^2> of the velocity field u ([D, *shape], compute dtype, as
+        moments() returns it; None: the current state's), central differences
+        of the given even order; waits for the stream."""
+        if u is None:
+            _, u, _, _ = self.moments()
+        u = self._need(u, (self.D,) + self.shape, self.dtype, "u")
+        self._stream()
+        out = ctypes.c_double()
+        check(_lib.lib().lbm_enstrophy(self._ctx, _ptr(u), int(order), ctypes.byref(out)), "lbm_enstrophy")
+        return out.value
+
     def sync(self):
         check(_lib.lib().lbm_sync(self._ctx), "lbm_sync")
 
