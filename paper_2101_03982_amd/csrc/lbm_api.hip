@@ -553,11 +553,18 @@ int lbm_init_equilibrium(lbm_ctx* c, const void* rho, const void* u, const void*
   return launch(c->k.init(p, c->stream), "init kernel");
 }
 
+// MI355X's last-level (Infinity) cache.  While both state buffers fit in it,
+// the step's output stays there for the next step's reads; beyond it, the
+// output is streamed past the caches (non-temporal stores), leaving them to
+// the halo rows that neighbouring tiles re-read.
+constexpr size_t LLC_BYTES = size_t(256) << 20;
+
 static int step_once(lbm_ctx* c, const void* src, void* dst) {
   KParams p = base_params(c);
   p.src = src;
   p.dst = dst;
-  return launch(c->k.mode[MODE_STEP](p, c->stream), "step kernel");
+  const StepLaunch f = (c->k.step_stream && 2 * c->state_bytes > LLC_BYTES) ? c->k.step_stream : c->k.mode[MODE_STEP];
+  return launch(f(p, c->stream), "step kernel");
 }
 
 int lbm_step(lbm_ctx* c, int64_t n) {

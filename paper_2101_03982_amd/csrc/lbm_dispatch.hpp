@@ -13,6 +13,8 @@ using CellLaunch = hipError_t (*)(const CellParams&, hipStream_t);
 
 struct Kernels {
   StepLaunch mode[4] = {nullptr, nullptr, nullptr, nullptr};  // indexed by Mode
+  // the forward step with non-temporal result stores (3D sets, n = 4 only)
+  StepLaunch step_stream = nullptr;
   CellLaunch init = nullptr;
   CellLaunch moments = nullptr;     // writes partials; grid = moments_blocks(ncell)
   CellLaunch ke_adjoint = nullptr;

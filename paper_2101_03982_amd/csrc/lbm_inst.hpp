@@ -16,7 +16,7 @@ inline void host_for(F&& f) {
   host_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
-template <int SET, int NS, int N, int A, int ST, int MODE>
+template <int SET, int NS, int N, int A, int ST, int MODE, int CP = 0>
 hipError_t launch_step(const KParams& p, hipStream_t s) {
   using R = typename StoreT<ST>::real;
   constexpr int D = Set<SET>::D;
@@ -40,7 +40,7 @@ hipError_t launch_step(const KParams& p, hipStream_t s) {
     q.chunk = q.tiles[0] * q.rsy * q.rsz;
   }
   const dim3 grid(unsigned(q.chunk) * 8u);
-  hipLaunchKernelGGL((sl_kernel<SET, NS, N, A, ST, MODE>), grid, dim3(TL::NT), 0, s, q);
+  hipLaunchKernelGGL((sl_kernel<SET, NS, N, A, ST, MODE, CP>), grid, dim3(TL::NT), 0, s, q);
   return hipGetLastError();
 }
 
@@ -82,6 +82,8 @@ bool find_kernels_part(int order, int arrays, Kernels* out) {
           found = true;
           *out = Kernels{};
           out->mode[MODE_STEP] = &launch_step<SET, NS, N, A, ST, MODE_STEP>;
+          if constexpr (Set<SET>::D == 3 && NS == 4)
+            out->step_stream = &launch_step<SET, NS, N, A, ST, MODE_STEP, CP_STREAM>;
           if constexpr (mode_built<SET, NS, N, A, ST, MODE_ADJ_COLLIDE>()) {
             out->mode[MODE_ADJ_COLLIDE] = &launch_step<SET, NS, N, A, ST, MODE_ADJ_COLLIDE>;
             out->mode[MODE_ADJ_STEP] = &launch_step<SET, NS, N, A, ST, MODE_ADJ_STEP>;

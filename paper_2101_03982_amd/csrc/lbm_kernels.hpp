@@ -62,8 +62,11 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
 // kahan: moment sums with compensated summation.
 // ldb/stb: buffer accesses at byte offset voff (per lane) + soff (uniform,
 // scalar register), so that a row offset shared by the block costs no vector
-// instruction.  The resource covers one population array (< 4 GiB).
+// instruction.  The resource covers one population array (< 4 GiB).  stb's
+// CP is the instruction's cache-policy field: 0, or CP_STREAM (the
+// non-temporal bit) for data that no later access of this launch reads.
 using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int CP_STREAM = 2;  // cache policy: non-temporal (streamed) store
 
 // Byte offset of element e for a buffer access, in unsigned 32-bit arithmetic
 // (the host keeps every population, plus one xy plane, below 4 GiB).
@@ -87,9 +90,10 @@ template <> struct StoreT<ST_F64> {
   static __device__ __forceinline__ real ldb(rsrc_t r, int voff, int soff) {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
   }
+  template <int CP = 0>
   static __device__ __forceinline__ void stb(real v, rsrc_t r, int voff, int soff) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned, v), r,
-                                          voff, soff, 0);
+                                          voff, soff, CP);
   }
   static __device__ __forceinline__ void ldb2(rsrc_t r, int voff, int soff, real& lo, real& hi) {
     // (elements copied to scalars first: bit-casting a vector element
@@ -108,8 +112,9 @@ template <> struct StoreT<ST_F32> {
   static __device__ __forceinline__ real ldb(rsrc_t r, int voff, int soff) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
   }
+  template <int CP = 0>
   static __device__ __forceinline__ void stb(real v, rsrc_t r, int voff, int soff) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, CP);
   }
   static __device__ __forceinline__ void ldb2(rsrc_t r, int voff, int soff, real& lo, real& hi) {
     const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
@@ -126,8 +131,9 @@ template <> struct StoreT<ST_BF16> {
   static __device__ __forceinline__ real ldb(rsrc_t r, int voff, int soff) {
     return bf16_to_f32(__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
   }
+  template <int CP = 0>
   static __device__ __forceinline__ void stb(real v, rsrc_t r, int voff, int soff) {
-    __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16(v), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16(v), r, voff, soff, CP);
   }
   static __device__ __forceinline__ void ldb2(rsrc_t r, int voff, int soff, real& lo, real& hi) {
     const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
@@ -143,8 +149,9 @@ template <> struct StoreT<ST_F16> {
   static __device__ __forceinline__ real ldb(rsrc_t r, int voff, int soff) {
     return float(__builtin_bit_cast(_Float16, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0)));
   }
+  template <int CP = 0>
   static __device__ __forceinline__ void stb(real v, rsrc_t r, int voff, int soff) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, _Float16(v)), r, voff, soff, 0);
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, _Float16(v)), r, voff, soff, CP);
   }
   static __device__ __forceinline__ void ldb2(rsrc_t r, int voff, int soff, real& lo, real& hi) {
     const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
@@ -886,7 +893,8 @@ constexpr int sl_min_waves() {
           cells_per_thread<Set<SET>::D, Set<SET>::Q, A, ST, MODE>() == 1) ? 4 : 1;
 }
 
-template <int SET, int NS, int N, int A, int ST, int MODE>
+// CP: cache policy of the result stores (0 or CP_STREAM).
+template <int SET, int NS, int N, int A, int ST, int MODE, int CP = 0>
 __global__ __launch_bounds__((sl_threads<SET, NS, A, ST, MODE>()), (sl_min_waves<SET, NS, A, ST, MODE>()))
 void sl_kernel(KParams p) {
   using S = Set<SET>;
@@ -1019,7 +1027,7 @@ void sl_kernel(KParams p) {
   };
   auto put_at = [&](int k, int r, R v) {  // store array k (population, or Q + population) of cell r
     if constexpr (D == 3)
-      TR::stb(v, make_rsrc(dst + int64_t(k) * p.pstride, p.pstride), boff<E>(lc_of(r)), rowb_of(r));
+      TR::template stb<CP>(v, make_rsrc(dst + int64_t(k) * p.pstride, p.pstride), boff<E>(lc_of(r)), rowb_of(r));
     else
       TR::st(at(dst + int64_t(k) * p.pstride, lc_of(r)), v);
   };
