@@ -1,7 +1,7 @@
 // Enstrophy E = <|curl u|^2> of a velocity field on the uniform periodic grid
 // (the diagnostic of Sec. 4.2), by central differences:
 //   d f / d x_a (x) ~ sum_{j=1..m} c_j (f(x + j e_a) - f(x - j e_a)) / dx.
-// One thread per node (grid-stride), FP64 arithmetic on the loaded values,
+// One wave per grid row (lanes along x), FP64 arithmetic on the loaded values,
 // block sums in a fixed tree order, then one block adds the block sums in
 // index order: the result does not depend on scheduling.
 #include "lbm_diag.hpp"
@@ -44,6 +44,11 @@ __device__ inline double ddx(const R* f, int64_t row, int64_t i, int64_t N, int6
   return s;
 }
 
+// One wave per grid row (y, z) at a time, its lanes along x: the row's
+// coordinates are found once per row (uniform), and every load of a
+// neighbour row is a coalesced row access.
+constexpr int DIAG_WAVES = DIAG_THREADS / 64;
+
 template <typename R, int D>
 __global__ __launch_bounds__(DIAG_THREADS) void enstrophy_kernel(CurlParams p) {
   const R* u = static_cast<const R*>(p.u);
@@ -51,19 +56,25 @@ __global__ __launch_bounds__(DIAG_THREADS) void enstrophy_kernel(CurlParams p) {
   const R* uy = u + p.ncell;
   const R* uz = u + 2 * p.ncell;
   const int64_t nx = p.n[0], ny = p.n[1], nz = p.n[2], nxy = nx * ny;
+  const int lane = threadIdx.x & 63;
+  const int64_t rows = ny * nz;
   double acc = 0.0;
-  for (int64_t e = int64_t(blockIdx.x) * DIAG_THREADS + threadIdx.x; e < p.ncell;
-       e += int64_t(gridDim.x) * DIAG_THREADS) {
-    const int64_t x = e % nx, y = (e / nx) % ny, z = e / nxy;
-    const int64_t rx = e - x, ry = e - y * nx, rz = e - z * nxy;
-    if constexpr (D == 3) {
-      const double wx = ddx(uz, ry, y, ny, nx, p) - ddx(uy, rz, z, nz, nxy, p);
-      const double wy = ddx(ux, rz, z, nz, nxy, p) - ddx(uz, rx, x, nx, 1, p);
-      const double wz = ddx(uy, rx, x, nx, 1, p) - ddx(ux, ry, y, ny, nx, p);
-      acc += wx * wx + wy * wy + wz * wz;
-    } else {
-      const double wz = ddx(uy, rx, x, nx, 1, p) - ddx(ux, ry, y, ny, nx, p);
-      acc += wz * wz;
+  for (int64_t row = int64_t(blockIdx.x) * DIAG_WAVES + (threadIdx.x >> 6); row < rows;
+       row += int64_t(gridDim.x) * DIAG_WAVES) {
+    const int64_t y = row % ny, z = row / ny;
+    const int64_t rowbase = row * nx;  // index of node (0, y, z)
+    for (int64_t x = lane; x < nx; x += 64) {
+      const int64_t e = rowbase + x;
+      const int64_t ry = e - y * nx, rz = e - z * nxy;
+      if constexpr (D == 3) {
+        const double wx = ddx(uz, ry, y, ny, nx, p) - ddx(uy, rz, z, nz, nxy, p);
+        const double wy = ddx(ux, rz, z, nz, nxy, p) - ddx(uz, rowbase, x, nx, 1, p);
+        const double wz = ddx(uy, rowbase, x, nx, 1, p) - ddx(ux, ry, y, ny, nx, p);
+        acc += wx * wx + wy * wy + wz * wz;
+      } else {
+        const double wz = ddx(uy, rowbase, x, nx, 1, p) - ddx(ux, ry, y, ny, nx, p);
+        acc += wz * wz;
+      }
     }
   }
   __shared__ double red[DIAG_THREADS];
@@ -101,7 +112,7 @@ hipError_t launch_enstrophy(const void* u, bool f64, const int64_t n[3], int D, 
   p.m = m;
   for (int j = 0; j < m; ++j) p.c[j] = coef[j];
   p.partial = partial;
-  const int64_t want = (p.ncell + DIAG_THREADS - 1) / DIAG_THREADS;
+  const int64_t want = (n[1] * n[2] + DIAG_WAVES - 1) / DIAG_WAVES;  // one wave per row
   const int blocks = want < 1 ? 1 : int(want < max_blocks ? want : max_blocks);
   if (f64) {
     if (D == 3) hipLaunchKernelGGL((enstrophy_kernel<double, 3>), dim3(blocks), dim3(DIAG_THREADS), 0, s, p);
