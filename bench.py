@@ -457,7 +457,7 @@ def svi_throughput(n=512):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path (got --gpus %d)" % a.gpus,
+        print("bench.py runs on one GPU: the library has no multi-GPU path (got --gpus %d)" % a.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch
