@@ -149,6 +149,74 @@ double momentum_norm(const lbm_ctx* c) {
   return 1.0 / s - 1.0;
 }
 
+// Moment defects of the FP32-rounded set (weights, abscissae and |xh|^2 as
+// the kernels round them) against the Gaussian moments, in the layout of
+// KParams::mdef; zero for FP64.
+void mass_defects(const lbm_ctx* c, double* out) {
+  for (int k = 0; k < MDEF_N; ++k) out[k] = 0.0;
+  if (compute_is_f64(c)) return;
+  const SetTable t = set_table(c->set);
+  const int D = c->D;
+  // exponents of the monomials (x, y, z) and their multiplicities
+  static const int quad[6][3] = {{2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
+  static const double quad_mult[6] = {1, 1, 1, 2, 2, 2};
+  static const int quart[15][3] = {{4, 0, 0}, {0, 4, 0}, {0, 0, 4}, {3, 1, 0}, {3, 0, 1}, {1, 3, 0}, {0, 3, 1},
+                                   {1, 0, 3}, {0, 1, 3}, {2, 2, 0}, {2, 0, 2}, {0, 2, 2}, {2, 1, 1}, {1, 2, 1},
+                                   {1, 1, 2}};
+  static const double quart_mult[15] = {1, 1, 1, 4, 4, 4, 4, 4, 4, 6, 6, 6, 12, 12, 12};
+  // Gaussian moment E[x^a y^b z^c] with unit variance: product of (k-1)!! for even k
+  auto gauss = [&](const int* e) {
+    double g = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      if (e[a] && a >= D) return 0.0;
+      if (e[a] % 2) return 0.0;
+      for (int k = e[a] - 1; k > 1; k -= 2) g *= k;
+    }
+    return g;
+  };
+  auto unused = [&](const int* e) {
+    for (int a = D; a < 3; ++a)
+      if (e[a]) return true;
+    return false;
+  };
+  double m0 = 0, mX = 0, mXX = 0, m2[6] = {0, 0, 0, 0, 0, 0}, mX2[6] = {0, 0, 0, 0, 0, 0};
+  double m4[15] = {0};
+  for (int i = 0; i < t.Q; ++i) {
+    const double w = double(float(t.w[i]));
+    double xe = 0;
+    for (int a = 0; a < 3; ++a) xe += t.xh[i][a] * t.xh[i][a];
+    const double X = double(float(xe));
+    double x[3];
+    for (int a = 0; a < 3; ++a) x[a] = double(float(t.xh[i][a]));
+    auto mono = [&](const int* e) {
+      double v = 1.0;
+      for (int a = 0; a < 3; ++a)
+        for (int k = 0; k < e[a]; ++k) v *= x[a];
+      return v;
+    };
+    m0 += w;
+    mX += w * X;
+    mXX += w * X * X;
+    for (int k = 0; k < 6; ++k) {
+      m2[k] += w * mono(quad[k]);
+      mX2[k] += w * X * mono(quad[k]);
+    }
+    for (int k = 0; k < 15; ++k) m4[k] += w * mono(quart[k]);
+  }
+  out[0] = m0 - 1.0;
+  out[7] = mX - D;
+  out[14] = mXX - double(D * (D + 2));
+  for (int k = 0; k < 6; ++k) {
+    if (unused(quad[k])) continue;
+    out[1 + k] = quad_mult[k] * (m2[k] - gauss(quad[k]));
+    out[8 + k] = quad_mult[k] * (mX2[k] - (D + 2) * gauss(quad[k]));
+  }
+  for (int k = 0; k < 15; ++k) {
+    if (unused(quart[k])) continue;
+    out[15 + k] = quart_mult[k] * (m4[k] - gauss(quart[k]));
+  }
+}
+
 KParams base_params(const lbm_ctx* c) {
   KParams p{};
   p.off = c->d_off;
@@ -170,6 +238,7 @@ KParams base_params(const lbm_ctx* c) {
   p.swX = c->swX;
   p.e64 = c->e64 ? 1.0 : 0.0;
   p.cmom1 = momentum_norm(c);
+  mass_defects(c, p.mdef);
   return p;
 }
 

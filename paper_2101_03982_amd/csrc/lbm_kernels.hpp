@@ -207,7 +207,17 @@ struct KParams {
   double swX;          // sum_i w_i |xh_i|^2
   double e64;          // nonzero: compressible energy moment summed in FP64
   double cmom1;        // 1 / sum_i w_i xh_ix^2 - 1 with the FP32-rounded constants
+  // FP32 compressible model: defects of the FP32-rounded set's moments against
+  // the Gaussian ones (MASS_* layout below), for the mass restoration
+  double mdef[30];
 };
+
+// Layout of KParams::mdef: [0] sum w - 1; [1..6] quadratic, [8..13]
+// |xh|^2-weighted quadratic moments, each times its multiplicity, monomials
+// xx yy zz xy xz yz; [7] sum w |xh|^2 - D; [14] sum w |xh|^4 - D(D+2);
+// [15..29] quartic moments times multiplicity, monomials xxxx yyyy zzzz
+// xxxy xxxz yyyx yyyz zzzx zzzy xxyy xxzz yyzz xxyz yyxz zzxy.
+constexpr int MDEF_N = 30;
 
 // Cells per thread along the register (outer) axis: every cell keeps its
 // A * Q interpolated values in registers until the collision.
@@ -845,6 +855,28 @@ __device__ __forceinline__ R peq_minus1(R a, R U, R eta, R X) {
 }
 
 // Derivatives of P with respect to a and U (weakly compressible, eta = 0).
+// sum_i w_i (P_i - 1) for the compressible N = 4 equilibrium with the rounded
+// constants, from the moment defects c = KParams::mdef: the sum is linear in
+// the set's moments and vanishes for the exact ones (Gaussian moments to
+// degree 4), so it is the same polynomial evaluated on the defects alone.
+template <int D, typename R>
+__device__ __forceinline__ R peq_mass_defect(const double* c, R ux, R uy, R uz, R U, R eta) {
+  const R x2 = ux * ux, y2 = uy * uy, z2 = uz * uz;
+  const R W2 = R(c[1]) * x2 + R(c[2]) * y2 + R(c[3]) * z2 + R(c[4]) * ux * uy + R(c[5]) * ux * uz + R(c[6]) * uy * uz;
+  const R WX2 = R(c[8]) * x2 + R(c[9]) * y2 + R(c[10]) * z2 + R(c[11]) * ux * uy + R(c[12]) * ux * uz +
+                R(c[13]) * uy * uz;
+  const R W4 = R(c[15]) * x2 * x2 + R(c[16]) * y2 * y2 + R(c[17]) * z2 * z2 + R(c[18]) * x2 * ux * uy +
+               R(c[19]) * x2 * ux * uz + R(c[20]) * y2 * uy * ux + R(c[21]) * y2 * uy * uz + R(c[22]) * z2 * uz * ux +
+               R(c[23]) * z2 * uz * uy + R(c[24]) * x2 * y2 + R(c[25]) * x2 * z2 + R(c[26]) * y2 * z2 +
+               R(c[27]) * x2 * uy * uz + R(c[28]) * y2 * ux * uz + R(c[29]) * z2 * ux * uy;
+  const R d0 = R(c[0]), dX = R(c[7]), dXX = R(c[14]);
+  R S = R(0.5) * (W2 - U * d0) + R(0.5) * eta * (dX - R(D) * d0);
+  const R t = W4 - R(6) * U * W2 + R(3) * U * U * d0 +
+              R(6) * eta * (WX2 - R(D + 4) * W2 - (dX - R(D + 2) * d0) * U) +
+              R(3) * eta * eta * (dXX - R(2 * (D + 2)) * dX + R(D * (D + 2)) * d0);
+  return fma(t, R(1.0 / 24.0), S);
+}
+
 template <int N, typename R>
 __device__ __forceinline__ void peq_derivs(R a, R U, R& P, R& Pa, R& PU) {
   R a2 = a * a;
@@ -1190,11 +1222,26 @@ void sl_kernel(KParams p) {
     // scaled by omega, where they are far above its rounding.  Neither changes the
     // other invariants (odd/even symmetry of the set).
     // 16-bit storage rounds far above these defects: no energy restoration there.
+    // The compressible model's Hermite terms (|u~|^2 up to ~6 at Ma 2) also carry
+    // the rounded even moments into the equilibrium's mass, sum_i w_i rho P_i =
+    // rho (1 + S) + (rho - 1) d0 with S, d0 ~ 1e-8 (peq_mass_defect): restored as
+    // w_i cM in the same non-equilibrium difference, cM = -(rho S + (rho - 1) d0)
+    // (sum_i w_i = 1 up to d0), and its energy cM sum_i w_i |xh_i|^2 counted in
+    // the energy balance after the small residual E_pre - E_eq has formed (added
+    // to the accumulator first it would fall below half an ulp of its terms).
     constexpr bool EFIX = COMP && DEV && !TR::kahan;
-    R Eeq[RO];
+    R Eeq[RO], cM[RO];
     double Eeq64[RO];
 #pragma unroll
-    for (int r = 0; r < RO; ++r) { Eeq[r] = R(0); Eeq64[r] = 0.0; }
+    for (int r = 0; r < RO; ++r) {
+      Eeq[r] = R(0);
+      Eeq64[r] = 0.0;
+      cM[r] = R(0);
+      if constexpr (EFIX) {
+        const Mom& m = mc[r];
+        cM[r] = -fma(m.rho, peq_mass_defect<D, R>(p.mdef, m.ux, m.uy, m.uz, m.U, m.eta), m.dr * R(p.mdef[0]));
+      }
+    }
     // populations outer, cells inner: each population's store address is set up once
     static_for<Q>([&](auto qc) {
       constexpr int q = decltype(qc)::value;
@@ -1215,6 +1262,7 @@ void sl_kernel(KParams p) {
         // f* = f + omega (f^eq - f): the small non-equilibrium part carries the rounding
         R df = feq_dev - ft[q][r];
         if constexpr (DEV && X != 0.0) df = fma(w * (m.rho * R(p.cmom1)), a, df);
+        if constexpr (EFIX) df = fma(w, cM[r], df);
         const R fo = fma(m.omega, df, ft[q][r]);
         put_at(q, r, SUBREF ? fo + w : fo);
         if constexpr (COMP) {
@@ -1237,8 +1285,8 @@ void sl_kernel(KParams p) {
       R cE[RO];
 #pragma unroll
       for (int r = 0; r < RO; ++r) {
-        cE[r] = (mc[r].Epre - Eeq[r]) * R(1.0 / p.sw);
-        if (p.e64 != 0.0) cE[r] = R((mc[r].Epre64 - Eeq64[r]) / p.sw);
+        cE[r] = ((mc[r].Epre - Eeq[r]) - cM[r] * R(p.swX)) * R(1.0 / p.sw);
+        if (p.e64 != 0.0) cE[r] = R(((mc[r].Epre64 - Eeq64[r]) - double(cM[r]) * p.swX) / p.sw);
       }
       static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;

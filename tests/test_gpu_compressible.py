@@ -201,14 +201,15 @@ def test_high_mach_ctgv_stays_stable(Ma):
     to t = 10 (562 / 841 steps), FP64 and FP32.  Every logged state keeps
     rho > 0 and theta > 0 with no non-finite value; mass and total energy stay
     conserved up to rounding (FP64: 1e-14 per step, a few units of 2^-53 in
-    the global sums; FP32: 1e-5); the kinetic energy decays overall; FP32's
+    the global sums; FP32: 1e-6, measured <= 1.5e-7 with the restoration of
+    the rounded constants' mass defect); the kinetic energy decays overall; FP32's
     kinetic-energy log stays within 1e-5 of FP64's."""
     wl = W.ctgv_workload(n=256, Ma=Ma, Re=400.0, dt=W.CTGV_PAPER_DT[Ma])
     steps = int(np.ceil(10.0 / wl.dt))
     logs = {st: _ctgv_log(wl, st, steps) for st in ("f64", "f32")}
     drift = {st: (max(abs(d.mass / log[0].mass - 1) for d in log), max(abs(d.energy / log[0].energy - 1) for d in log))
              for st, log in logs.items()}
-    for st, tol in (("f64", 1e-14 * steps), ("f32", 1e-5)):
+    for st, tol in (("f64", 1e-14 * steps), ("f32", 1e-6)):
         log = logs[st]
         assert all(d.nonfinite == 0 and d.min_rho > 0 and d.min_theta > 0 for d in log)
         assert max(drift[st]) <= tol, drift
