@@ -153,11 +153,12 @@ int lbm_init_equilibrium(lbm_ctx *ctx, const void *rho, const void *u, const voi
 /* Advances the bound state by n >= 0 time steps (stream, then collide); each
  * step reads the current buffer and writes the other one, which then becomes
  * current.  n = 0 does nothing.  With float arithmetic (all storages but
- * LBM_F64) the collision also restores the momentum, and in the compressible
- * model the energy, that the float-rounded set constants would miss
- * (sum_i w_i xi_i xi_i equals c_s^2 I only to ~1e-8 there), so that these
- * collision invariants (Sec. 3) hold to rounding as in FP64.  Buffers need
- * the element type's alignment; an even-element alignment is faster. */
+ * LBM_F64) the collision also restores the momentum, and with LBM_F32 in the
+ * compressible model the mass and the energy, that the float-rounded set
+ * constants would miss (sum_i w_i xi_i xi_i equals c_s^2 I only to ~1e-8
+ * there), so that these collision invariants (Sec. 3) hold to rounding as in
+ * FP64.  Buffers need the element type's alignment; an even-element alignment
+ * is faster. */
 int lbm_step(lbm_ctx *ctx, int64_t n);
 
 /* One time step from src to dst (caller device buffers of lbm_state_bytes(),
