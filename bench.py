@@ -528,11 +528,22 @@ def main():
         torch.cuda.synchronize()
         ms = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
         avg_ms = sum(ms) / len(ms)
+        # the diagnostics call (moments kernel, block-sum reduction, 72-byte copy
+        # to the host; it waits for the stream), separately from the step
+        mom = []
+        for _ in range(10):
+            m0, m1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            m0.record(stream)
+            lat.moments(fields=False)
+            m1.record(stream)
+            torch.cuda.synchronize()
+            mom.append(m0.elapsed_time(m1))
         bpc = 2 * lat.Q * 4  # one FP32 read and one write of every population per cell update
         gbs = bpc * wl.ncell / (avg_ms * 1e-3) / 1e9
         per_set[s] = {"kernel_ms": avg_ms, "kernel_ms_median": ms[len(ms) // 2],
                       "mlups": wl.ncell / (avg_ms * 1e-3) / 1e6, "bytes_per_cell": bpc,
                       "achieved_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                      "moments_ms": sorted(mom)[len(mom) // 2],
                       "ke_log": ke_log[s][-3:]}
     dominant = max(per_set, key=lambda s: per_set[s]["kernel_ms"])
     dom = per_set[dominant]
