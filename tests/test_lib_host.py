@@ -156,3 +156,76 @@ def test_lattice_refuses_cpu_device():
 
     with pytest.raises(ValueError):
         Lattice("D2Q9", (8, 8), tau=0.8, device=torch.device("cpu"))
+
+
+# Monomial orders of the compressible FP32 kernels' mass-defect coefficients.
+_QUAD = [(2, 0, 0), (0, 2, 0), (0, 0, 2), (1, 1, 0), (1, 0, 1), (0, 1, 1)]
+_QUAD_MULT = [1, 1, 1, 2, 2, 2]
+_QUART = [(4, 0, 0), (0, 4, 0), (0, 0, 4), (3, 1, 0), (3, 0, 1), (1, 3, 0), (0, 3, 1), (1, 0, 3), (0, 1, 3),
+          (2, 2, 0), (2, 0, 2), (0, 2, 2), (2, 1, 1), (1, 2, 1), (1, 1, 2)]
+_QUART_MULT = [1, 1, 1, 4, 4, 4, 4, 4, 4, 6, 6, 6, 12, 12, 12]
+
+
+@pytest.mark.parametrize("name", ["D2Q19", "D2Q25", "D3Q45"])
+def test_mass_defect_identity(name):
+    """The FP32 compressible collision restores the equilibrium's mass from
+    sum_i fl(w_i) (P_i - 1), which is linear in the rounded set's moments and
+    zero for exact (Gaussian) ones; so it equals the N = 4 Hermite polynomial
+    of App. A evaluated on the moment defects alone.  Checked in exact
+    rational arithmetic on the library's own tables with float-rounded
+    weights, abscissae and |xh|^2, for random u~ and theta - 1."""
+    from fractions import Fraction as F
+
+    from paper_2101_03982_amd import set_table
+
+    t = set_table(name)
+    D = len(t["xi"][0])
+    f32 = lambda v: F(float(np.float32(v)))  # noqa: E731
+    xh = [[x / t["cs"] for x in row] + [0.0] * (3 - D) for row in t["xi"]]
+    w = [f32(v) for v in t["w"]]
+    x = [[f32(c) for c in row] for row in xh]
+    X = [f32(sum(c * c for c in row)) for row in xh]
+
+    def mono(v, e):
+        return v[0] ** e[0] * v[1] ** e[1] * v[2] ** e[2]
+
+    def gauss(e):
+        if any(e[a] for a in range(D, 3)) or any(k % 2 for k in e):
+            return 0
+        g = 1
+        for k in e:
+            g *= max(1, int(np.prod(range(k - 1, 0, -2))))
+        return g
+
+    c = [F(0)] * 30
+    c[0] = sum(w) - 1
+    c[7] = sum(wi * Xi for wi, Xi in zip(w, X)) - D
+    c[14] = sum(wi * Xi * Xi for wi, Xi in zip(w, X)) - D * (D + 2)
+    for k, e in enumerate(_QUAD):
+        c[1 + k] = _QUAD_MULT[k] * (sum(wi * mono(xi, e) for wi, xi in zip(w, x)) - gauss(e))
+        c[8 + k] = _QUAD_MULT[k] * (sum(wi * Xi * mono(xi, e) for wi, xi, Xi in zip(w, x, X)) - (D + 2) * gauss(e))
+    for k, e in enumerate(_QUART):
+        c[15 + k] = _QUART_MULT[k] * (sum(wi * mono(xi, e) for wi, xi in zip(w, x)) - gauss(e))
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        u = [F(float(v)) for v in rng.normal(size=3) * 1.2]
+        if D == 2:
+            u[2] = F(0)
+        eta = F(float(rng.normal() * 0.2))
+        U = sum(v * v for v in u)
+        direct = F(0)
+        for wi, xi, Xi in zip(w, x, X):
+            a = sum(p * q for p, q in zip(xi, u))
+            s = a + (a * a - U) / 2 + eta * (Xi - D) / 2 + (a * (a * a - 3 * U) + 3 * eta * a * (Xi - D - 2)) / 6
+            s += (a ** 4 - 6 * a * a * U + 3 * U * U + 6 * eta * ((Xi - D - 4) * a * a - (Xi - D - 2) * U)
+                  + 3 * eta * eta * (Xi * Xi - 2 * (D + 2) * Xi + D * (D + 2))) / 24
+            direct += wi * s
+        W2 = sum(c[1 + k] * mono(u, e) for k, e in enumerate(_QUAD))
+        WX2 = sum(c[8 + k] * mono(u, e) for k, e in enumerate(_QUAD))
+        W4 = sum(c[15 + k] * mono(u, e) for k, e in enumerate(_QUART))
+        d0, dX, dXX = c[0], c[7], c[14]
+        S = (W2 - U * d0) / 2 + eta * (dX - D * d0) / 2
+        S += (W4 - 6 * U * W2 + 3 * U * U * d0 + 6 * eta * (WX2 - (D + 4) * W2 - (dX - (D + 2) * d0) * U)
+              + 3 * eta * eta * (dXX - 2 * (D + 2) * dX + D * (D + 2) * d0)) / 24
+        assert S == direct
+        assert 0 < abs(float(direct)) < 1e-6  # a small but non-zero defect
