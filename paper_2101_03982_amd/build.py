@@ -37,6 +37,23 @@ FLAGS = [
 ]
 
 
+# Extra compiler flags per unit name prefix.  The 16-bit D3Q45 f + g kernels
+# run 2.5 % (BF16) and 4.4 % (FP16) faster at 256^3 with LLVM's ILP-oriented
+# machine scheduler; every other kernel measured 1-27 % slower with it.
+UNIT_FLAGS = {
+    "part_D3Q45_bf16_": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+    "part_D3Q45_f16_": ["-mllvm", "-amdgpu-sched-strategy=max-ilp"],
+}
+
+
+def unit_flags(path):
+    name = os.path.basename(path)
+    for prefix, flags in UNIT_FLAGS.items():
+        if name.startswith(prefix):
+            return flags
+    return []
+
+
 def parts():
     """(name, source text) of every kernel-table unit."""
     out = []
@@ -74,7 +91,7 @@ def _stale(src, obj):
 def _compile(src, obj, force=True):
     if not force and not _stale(src, obj):
         return obj, 0.0
-    cmd = [HIPCC, *FLAGS, "-I", CSRC, "-c", src, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *unit_flags(src), "-I", CSRC, "-c", src, "-o", obj]
     t0 = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
