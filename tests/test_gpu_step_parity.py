@@ -133,25 +133,29 @@ def test_unaligned_buffers_match_aligned(orc, storage):
     assert torch.equal(dst.view(ints), out_a.view(ints))
 
 
-def test_streamed_stores_match_cached_stores():
+@pytest.mark.parametrize("storage,small", [("f32", (128, 128, 64)), ("f64", (128, 64, 64)),
+                                           ("bf16", (128, 128, 128))])
+def test_streamed_stores_match_cached_stores(storage, small):
     """When the two state buffers exceed the 256 MB last-level cache, the 3D
     n = 4 step stores its results with the non-temporal cache policy.  The
-    values are the same bit for bit: a 128^3 D3Q27 FP32 lattice (two buffers
-    453 MB, streamed stores) holding two periodic copies of a 128 x 128 x 64
-    one (226 MB, cached stores) steps to two copies of the smaller one's
-    result."""
+    values are the same bit for bit: a D3Q27 lattice holding two periodic
+    copies (along z) of a smaller one whose two buffers fit (226 MB, cached
+    stores; the doubled lattice 453 MB, streamed stores) steps to two copies
+    of the smaller one's result, for FP32, FP64 and BF16 storage."""
     name = "D3Q27"
     cs = 0.6
     dt = 0.45 / (W.MAX_COMPONENT_OVER_CS[name] * cs)
-    kw = dict(stencil=4, storage="f32", dx=1.0, dt=dt, cs=cs, device="cuda:0")
-    small = Lattice(name, (128, 128, 64), 0.57, 2, **kw)
-    big = Lattice(name, (128, 128, 128), 0.57, 2, **kw)
-    rho, u, _ = W.random_fields(3, small.shape, 21, u_amp=0.1 * cs, rho_amp=0.02)
-    small.init_equilibrium(to_dev(rho, torch.float32), to_dev(u, torch.float32))
-    big.init_equilibrium(to_dev(np.concatenate([rho, rho], axis=0), torch.float32),
-                         to_dev(np.concatenate([u, u], axis=1), torch.float32))
-    small.step(3)
-    big.step(3)
-    a = small.state().view(torch.int32)
-    b = big.state().view(torch.int32)
-    assert torch.equal(b[:, :64], a) and torch.equal(b[:, 64:], a)
+    kw = dict(stencil=4, storage=storage, dx=1.0, dt=dt, cs=cs, device="cuda:0")
+    nx, ny, nz = small
+    lo = Lattice(name, small, 0.57, 2, **kw)
+    hi = Lattice(name, (nx, ny, 2 * nz), 0.57, 2, **kw)
+    rho, u, _ = W.random_fields(3, lo.shape, 21, u_amp=0.1 * cs, rho_amp=0.02)
+    lo.init_equilibrium(to_dev(rho, lo.dtype), to_dev(u, lo.dtype))
+    hi.init_equilibrium(to_dev(np.concatenate([rho, rho], axis=0), hi.dtype),
+                        to_dev(np.concatenate([u, u], axis=1), hi.dtype))
+    lo.step(3)
+    hi.step(3)
+    ints = {"f32": torch.int32, "f64": torch.int64, "bf16": torch.int16}[storage]
+    a = lo.state().view(ints)
+    b = hi.state().view(ints)
+    assert torch.equal(b[:, :nz], a) and torch.equal(b[:, nz:], a)
