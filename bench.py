@@ -40,7 +40,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=128, help="grid points per axis")
-    ap.add_argument("--log-every", type=int, default=50)
+    ap.add_argument("--log-every", type=int, default=None,
+                    help="kinetic-energy log interval in steps (default: 50, or --steps if fewer, so that the "
+                         "timed window always holds at least one log)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the FP64-error, adjoint-cost, dissipation, reduced-precision and high-Mach measurements")
@@ -51,7 +53,15 @@ def parse():
                     help="streams the lattices step on (0: one per lattice, 1: all on the current stream)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
-    return ap.parse_args()
+    ap.add_argument("--only", default=None,
+                    help="run one leg alone and print its JSON (precision, svi, svi2048, adjoint, large_grid); "
+                         "with --precision-steps and --storages it is the profiling target of one kernel family")
+    ap.add_argument("--storages", default="f64,f32,bf16,f16", help="storages of the precision leg")
+    ap.add_argument("--machs", default="0.5,1.0", help="Mach numbers of the precision leg")
+    a = ap.parse_args()
+    if a.log_every is None:
+        a.log_every = min(50, a.steps)
+    return a
 
 
 def kernel_sha():
@@ -263,7 +273,7 @@ def high_mach(n=256, t_end=10.0, machs=(0.5, 1.0, 1.5, 2.0), storage="f32", ever
     return res
 
 
-def precision_form(n=256, steps=1000, machs=(0.5, 1.0)):
+def precision_form(n=256, steps=1000, machs=(0.5, 1.0), storages=("f64", "f32", "bf16", "f16")):
     """Compressible TGV with D3Q45 (N = 4, n = 4): time per step and error
     after `steps` steps of the BF16/FP16 deviation storage and of FP32 against
     the FP64 run on the same GPU."""
@@ -279,7 +289,7 @@ def precision_form(n=256, steps=1000, machs=(0.5, 1.0)):
         rho_np, u_np, th_np = W.ctgv_fields(wl)
         ref = None
         entry = {}
-        for st in ("f64", "f32", "bf16", "f16"):
+        for st in storages:
             lat = Lattice("D3Q45", wl.grid, wl.tau, 4, stencil=wl.stencil, storage=st, dx=wl.dx, dt=wl.dt,
                           cs=wl.cs, compressible=True, gamma=wl.gamma,
                           energy_f64=(st in ("bf16", "f16") and Ma >= 1.0),
@@ -287,14 +297,15 @@ def precision_form(n=256, steps=1000, machs=(0.5, 1.0)):
             dt_ = lat.dtype
             lat.init_equilibrium(torch.from_numpy(rho_np).to("cuda:0", dt_), torch.from_numpy(u_np).to("cuda:0", dt_),
                                  torch.from_numpy(th_np).to("cuda:0", dt_))
-            lat.step(5)
+            warm = min(5, steps - 1)
+            lat.step(warm)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            lat.step(steps - 5)
+            lat.step(steps - warm)
             e1.record()
             torch.cuda.synchronize()
-            ms = e0.elapsed_time(e1) / (steps - 5)
+            ms = e0.elapsed_time(e1) / (steps - warm)
             try:
                 r, u, th, d = lat.moments()
                 fields = (r.double(), u.double(), th.double())
@@ -302,8 +313,9 @@ def precision_form(n=256, steps=1000, machs=(0.5, 1.0)):
             except Exception as exc:  # noqa: BLE001 - reported in the JSON
                 fields, d, ok = None, None, str(exc)
             bpc = 2 * 90 * {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}[st]
-            e = {"ms_per_step": ms, "mlups": wl.ncell / (ms * 1e-3) / 1e6,
-                 "achieved_GBs": bpc * wl.ncell / (ms * 1e-3) / 1e9, "ok": ok}
+            gbs = bpc * wl.ncell / (ms * 1e-3) / 1e9
+            e = {"ms_per_step": ms, "mlups": wl.ncell / (ms * 1e-3) / 1e6, "bytes_per_cell": bpc,
+                 "achieved_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS, "ok": ok}
             if ok is True:
                 e["ke"] = d.ke
                 if st == "f64":
@@ -319,9 +331,9 @@ def precision_form(n=256, steps=1000, machs=(0.5, 1.0)):
             lat.close()
             del lat
             torch.cuda.empty_cache()
-        if "f32" in entry and "bf16" in entry:
-            entry["speedup_bf16_over_f32"] = entry["f32"]["ms_per_step"] / entry["bf16"]["ms_per_step"]
-            entry["speedup_f16_over_f32"] = entry["f32"]["ms_per_step"] / entry["f16"]["ms_per_step"]
+        for st in ("bf16", "f16"):
+            if "f32" in entry and st in entry:
+                entry["speedup_%s_over_f32" % st] = entry["f32"]["ms_per_step"] / entry[st]["ms_per_step"]
         res["Ma%.1f" % Ma] = entry
     res["workload"] = "compressible TGV (CTIC) D3Q45 f+g, N = 4, n = 4, %d^3, Re 1600, %d steps" % (n, steps)
     return res
@@ -428,7 +440,9 @@ def on_lattice_ratio(n=128):
 
 def svi_throughput(n=512):
     """Shock-vortex workload (D2Q19 / D2Q25, f + g, N = 4, n = 5, extrapolating
-    in x) at its full 512^2 size: single-launch time per set and storage."""
+    in x) at n^2 (512^2, the workload's size, whose two buffers fit in the
+    256 MB Infinity Cache; 2048^2, 1.3-3.4 GB, for HBM's rate): single-launch
+    time per set and storage."""
     import torch
 
     import lbm_inputs as W
@@ -457,6 +471,39 @@ def svi_throughput(n=512):
     return out
 
 
+def run_only(a):
+    """One leg alone (profiling target)."""
+    legs = {
+        "precision": lambda: precision_form(a.precision_n, a.precision_steps,
+                                            tuple(float(m) for m in a.machs.split(",")),
+                                            tuple(a.storages.split(","))),
+        "svi": lambda: svi_throughput(512),
+        "svi2048": lambda: svi_throughput(2048),
+        "adjoint": adjoint_cost,
+        "large_grid": large_grid,
+    }
+    if a.only not in legs:
+        print("unknown leg %r (one of %s)" % (a.only, ", ".join(sorted(legs))), file=sys.stderr)
+        sys.exit(2)
+    if a.copy_probe:
+        copy_probe()
+    print(json.dumps({"leg": a.only, a.only: legs[a.only]()}), flush=True)
+
+
+def copy_probe():
+    """A plain 1 GiB device-to-device copy (1 GiB read, 1 GiB written): the
+    known-size kernel that calibrates the HBM byte counters."""
+    import torch
+
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -471,15 +518,13 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if a.only:
+        run_only(a)
+        return
     dev = torch.device("cuda:0")
     sets = tuple(a.sets.split(","))
     if a.copy_probe:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_probe()
     lats = []
     for s in sets:
         wl = W.tgv3d_workload(s, n=a.n)
@@ -591,6 +636,7 @@ def main():
         out["adjoint"] = adjoint_cost()
         out["large_grid"] = large_grid()
         out["svi"] = svi_throughput()
+        out["svi_2048"] = svi_throughput(2048)
         out["on_lattice"] = on_lattice_ratio()
         out["dissipation"] = dissipation(sets)
         torch.cuda.empty_cache()

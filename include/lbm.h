@@ -87,7 +87,8 @@ typedef struct lbm_options {
   int32_t stencil;       /* Lagrange nodes per axis n, 1..5 */
   int32_t compressible;  /* 0: f only, theta = 1; 1: f and g (Sec. 3) */
   int32_t boundary[3];   /* lbm_boundary per axis x, y, z */
-  int32_t energy_f64;    /* deviation storage, compressible: sum the energy moment in FP64 */
+  int32_t energy_f64;    /* 16-bit storage, compressible: sum the energy moment in FP64
+                            (LBM_EUNSUPPORTED with any other storage or model) */
   int32_t reserved;
   double dx;             /* grid spacing (> 0) */
   double dt;             /* time step (> 0) */
@@ -145,10 +146,27 @@ int lbm_bind(lbm_ctx *ctx, void *buf0, void *buf1);
 /* Device pointer of the buffer that holds the current state. */
 void *lbm_state(lbm_ctx *ctx);
 
-/* Writes f = f^eq(rho, u, theta) (and g = g^eq) into the current buffer.
- * rho [cells], u [D][cells] (physical units), theta [cells] or NULL
- * (theta = 1), all device arrays of the compute type. */
+/* Writes f = f^eq(rho, u, theta) (and g = g^eq) into the current buffer:
+ * the Hermite equilibrium of Sec. 3 truncated at the context's order N, with
+ * the moments and Hermite tensors of App. A (T0 = c_s^2), and in the
+ * compressible model g^eq = theta (2 C_v - D) f^eq (Sec. 3).  rho [cells],
+ * u [D][cells] (physical units), theta [cells] or NULL (theta = 1), all
+ * device arrays of the compute type, read on the context's stream.
+ * LBM_EINVAL: null rho or u, or no buffers bound. */
 int lbm_init_equilibrium(lbm_ctx *ctx, const void *rho, const void *u, const void *theta);
+
+/* Checkpoint and resume: copies the current state (lbm_state_bytes() bytes,
+ * the population layout above, as stored) to dst, or from src into the
+ * current buffer.  dst/src may be device memory or host memory (pinned or
+ * pageable); the copy is ordered on the context's stream after all work
+ * enqueued before it, and the call returns once it has completed, so a host
+ * buffer is ready (get) or reusable (set) on return.  A state saved with
+ * lbm_get_state and restored with lbm_set_state into a context created with
+ * the same arguments steps on bit for bit as the original.  The caller owns
+ * dst/src.  LBM_EINVAL: null pointer or no buffers bound; LBM_EHIP: copy
+ * failure (including earlier asynchronous faults). */
+int lbm_get_state(lbm_ctx *ctx, void *dst);
+int lbm_set_state(lbm_ctx *ctx, const void *src);
 
 /* Advances the bound state by n >= 0 time steps (stream, then collide); each
  * step reads the current buffer and writes the other one, which then becomes
@@ -228,11 +246,13 @@ int lbm_init_equilibrium_adjoint(lbm_ctx *ctx, const void *rho, const void *u, c
 
 /* ---- Host-only helpers (no GPU needed) ---- */
 
-/* The per-direction stencil the kernels use, computed on the host: for every
+/* The per-direction stencil of the semi-Lagrangian streaming (Sec. 3, eq.
+ * sl_streaming: f_i at the departure point x - xi_i dt, as a sum of node
+ * values times interpolation polynomials), computed on the host: for every
  * population i and axis a, offsets[3*i + a] is the offset of the first
- * stencil node from the arrival node and weights[(3*i + a)*n + k] the weight
- * of node k, for a set scaled to speed of sound cs (<= 0: the table's own)
- * with time step dt and spacing dx.  An axis along which xi_i has no
+ * stencil node from the arrival node and weights[(3*i + a)*n + k] the
+ * Lagrange weight of node k at the departure point, for a set scaled to
+ * speed of sound cs (<= 0: the table's own) with time step dt and spacing dx.  An axis along which xi_i has no
  * component gets offset 0 and the single weight 1 followed by zeros.  The
  * weights are exact FP64 Lagrange weights (not the quantized ones the kernels
  * use).  Arrays hold Q*3 and Q*3*n entries. */
@@ -241,6 +261,19 @@ int lbm_stencil(int32_t set, double dt, double dx, double cs, int32_t n, int32_t
 /* The library's velocity set table: Q, D, degree, table speed of sound,
  * weights w[Q] and abscissae xi[Q][3] in table units. */
 int lbm_set_table(int32_t set, int32_t *Q, int32_t *D, int32_t *degree, double *cs, double *w, double *xi);
+
+/* The 30 coefficients with which the float (LBM_F32) compressible collision
+ * restores the equilibrium's mass (lbm_step): the defects of the set's
+ * moments, with its weights, abscissae and |xh|^2 rounded to float, against
+ * the Gaussian moments they replace (degree 0, 2 and 4, in table units
+ * xh = xi / c_s), each times the multiplicity of its monomial.  out[0]:
+ * sum w - 1; out[1..6]: quadratic moments, monomials xx yy zz xy xz yz;
+ * out[7]: sum w |xh|^2 - D; out[8..13]: |xh|^2-weighted quadratic moments
+ * minus (D + 2) times the Gaussian ones, same monomials; out[14]:
+ * sum w |xh|^4 - D (D + 2); out[15..29]: quartic moments, monomials xxxx
+ * yyyy zzzz xxxy xxxz yyyx yyyz zzzx zzzy xxyy xxzz yyzz xxyz yyxz zzxy.
+ * Monomials along axes the set lacks are 0.  Host-only; out holds 30. */
+int lbm_float_moment_defects(int32_t set, double *out);
 
 const char *lbm_strerror(int status);
 const char *lbm_last_error(void);

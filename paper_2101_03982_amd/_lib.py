@@ -67,6 +67,8 @@ _SIGS = {
     "lbm_bind": (ctypes.c_int, [_V, _P, _P]),
     "lbm_state": (_P, [_V]),
     "lbm_init_equilibrium": (ctypes.c_int, [_V, _P, _P, _P]),
+    "lbm_get_state": (ctypes.c_int, [_V, _P]),
+    "lbm_set_state": (ctypes.c_int, [_V, _P]),
     "lbm_step": (ctypes.c_int, [_V, _I64]),
     "lbm_step_into": (ctypes.c_int, [_V, _P, _P]),
     "lbm_moments": (ctypes.c_int, [_V, _P, _P, _P, _P, ctypes.POINTER(Diag)]),
@@ -79,6 +81,7 @@ _SIGS = {
     "lbm_adjoint_step": (ctypes.c_int, [_V, _P, _P, _P]),
     "lbm_ke_adjoint": (ctypes.c_int, [_V, _P, _P]),
     "lbm_init_equilibrium_adjoint": (ctypes.c_int, [_V, _P, _P, _P, _P]),
+    "lbm_float_moment_defects": (ctypes.c_int, [_I32, ctypes.POINTER(_D)]),
     "lbm_stencil": (ctypes.c_int, [_I32, _D, _D, _D, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_D)]),
     "lbm_set_table": (ctypes.c_int, [_I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                                      ctypes.POINTER(_D), ctypes.POINTER(_D), ctypes.POINTER(_D)]),

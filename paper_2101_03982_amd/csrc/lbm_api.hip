@@ -151,12 +151,10 @@ double momentum_norm(const lbm_ctx* c) {
 
 // Moment defects of the FP32-rounded set (weights, abscissae and |xh|^2 as
 // the kernels round them) against the Gaussian moments, in the layout of
-// KParams::mdef; zero for FP64.
-void mass_defects(const lbm_ctx* c, double* out) {
-  for (int k = 0; k < MDEF_N; ++k) out[k] = 0.0;
-  if (compute_is_f64(c)) return;
-  const SetTable t = set_table(c->set);
-  const int D = c->D;
+// KParams::mdef.
+void float_moment_defects(int set, double* out) {
+  const SetTable t = set_table(set);
+  const int D = t.D;
   // exponents of the monomials (x, y, z) and their multiplicities
   static const int quad[6][3] = {{2, 0, 0}, {0, 2, 0}, {0, 0, 2}, {1, 1, 0}, {1, 0, 1}, {0, 1, 1}};
   static const double quad_mult[6] = {1, 1, 1, 2, 2, 2};
@@ -203,6 +201,7 @@ void mass_defects(const lbm_ctx* c, double* out) {
     }
     for (int k = 0; k < 15; ++k) m4[k] += w * mono(quart[k]);
   }
+  for (int k = 0; k < MDEF_N; ++k) out[k] = 0.0;
   out[0] = m0 - 1.0;
   out[7] = mX - D;
   out[14] = mXX - double(D * (D + 2));
@@ -215,6 +214,14 @@ void mass_defects(const lbm_ctx* c, double* out) {
     if (unused(quart[k])) continue;
     out[15 + k] = quart_mult[k] * (m4[k] - gauss(quart[k]));
   }
+}
+
+void mass_defects(const lbm_ctx* c, double* out) {
+  if (compute_is_f64(c)) {
+    for (int k = 0; k < MDEF_N; ++k) out[k] = 0.0;
+    return;
+  }
+  float_moment_defects(c->set, out);
 }
 
 KParams base_params(const lbm_ctx* c) {
@@ -401,6 +408,13 @@ int lbm_set_table(int32_t set, int32_t* Q, int32_t* D, int32_t* degree, double* 
   return LBM_OK;
 }
 
+int lbm_float_moment_defects(int32_t set, double* out) {
+  if (set < 0 || set >= NUM_SETS) return fail(LBM_EINVAL, "unknown velocity set");
+  if (!out) return fail(LBM_EINVAL, "null pointer");
+  float_moment_defects(set, out);
+  return LBM_OK;
+}
+
 int lbm_stencil(int32_t set, double dt, double dx, double cs, int32_t n, int32_t* offsets, double* weights) {
   if (set < 0 || set >= NUM_SETS) return fail(LBM_EINVAL, "unknown velocity set");
   if (n < 1 || n > MAXNS) return fail(LBM_EINVAL, "stencil length must be 1..5");
@@ -475,6 +489,8 @@ int lbm_create(lbm_ctx** out, int32_t set, const int64_t grid[3], double tau, in
   c->gamma = o.gamma;
   if (c->A == 2 && !(o.gamma > 1.0)) return bad(LBM_EINVAL, "gamma must exceed 1");
   c->e64 = o.energy_f64 ? 1 : 0;
+  if (c->e64 && (c->A != 2 || (o.storage != LBM_BF16DEV && o.storage != LBM_F16DEV)))
+    return bad(LBM_EUNSUPPORTED, "energy_f64 applies to the compressible model with 16-bit storage");
   for (int a = 0; a < 3; ++a) {
     if (o.boundary[a] != LBM_PERIODIC && o.boundary[a] != LBM_EXTRAPOLATE) return bad(LBM_EINVAL, "unknown boundary");
     c->bc[a] = (a < c->D) ? o.boundary[a] : LBM_PERIODIC;
@@ -622,6 +638,32 @@ int lbm_init_equilibrium(lbm_ctx* c, const void* rho, const void* u, const void*
   return launch(c->k.init(p, c->stream), "init kernel");
 }
 
+// Stream-ordered copy of the whole current state; waits for it so that a
+// host buffer is complete (or reusable) when the call returns.
+static int copy_state(lbm_ctx* c, void* dst, const void* src, const char* what) {
+  hipError_t e = hipMemcpyAsync(dst, src, c->state_bytes, hipMemcpyDefault, c->stream);
+  if (e != hipSuccess) return hip_fail(e, what);
+  e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+  return LBM_OK;
+}
+
+int lbm_get_state(lbm_ctx* c, void* dst) {
+  if (int r = check_ctx(c)) return r;
+  if (!c->buf[0]) return fail(LBM_EINVAL, "no buffers bound");
+  if (!dst) return fail(LBM_EINVAL, "null destination");
+  if (int r = set_device(c)) return r;
+  return copy_state(c, dst, c->buf[c->cur], "hipMemcpyAsync (get state)");
+}
+
+int lbm_set_state(lbm_ctx* c, const void* src) {
+  if (int r = check_ctx(c)) return r;
+  if (!c->buf[0]) return fail(LBM_EINVAL, "no buffers bound");
+  if (!src) return fail(LBM_EINVAL, "null source");
+  if (int r = set_device(c)) return r;
+  return copy_state(c, c->buf[c->cur], src, "hipMemcpyAsync (set state)");
+}
+
 // MI355X's last-level (Infinity) cache.  While both state buffers fit in it,
 // the step's output stays there for the next step's reads; beyond it, the
 // output is streamed past the caches (non-temporal stores), leaving them to
@@ -659,40 +701,47 @@ int lbm_step_into(lbm_ctx* c, const void* src, void* dst) {
   return step_once(c, src, dst);
 }
 
-int lbm_moments(lbm_ctx* c, const void* state, void* rho, void* u, void* theta, lbm_diag* diag) {
-  if (int r = check_ctx(c)) return r;
-  if (!state) state = c->buf[c->cur];
-  if (!state) return fail(LBM_EINVAL, "no state");
-  if (int r = set_device(c)) return r;
+// The moments kernel's block sums into `partial` ([nblocks][NPART]), their
+// sum into `result` ([NPART]), copied to the host array `host` ([NPART]);
+// waits for the stream.
+static int moments_impl(lbm_ctx* c, const void* state, void* rho, void* u, void* theta, lbm_diag* diag,
+                        double* partial, double* result, double* host) {
   CellParams p = base_cell(c);
   p.f = state;
   p.out_rho = rho;
   p.out_u = u;
   p.out_theta = theta;
-  p.partial = c->d_partial;
+  p.partial = partial;
+  p.nblocks = moment_blocks(c->ncell);
   if (int r = launch(c->k.moments(p, c->stream), "moments kernel")) return r;
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, c->stream, c->d_partial, MOMENT_BLOCKS,
-                     c->d_result);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, c->stream, partial, p.nblocks, result);
   if (int r = launch(hipGetLastError(), "reduce kernel")) return r;
-  hipError_t e = hipMemcpyAsync(c->h_result, c->d_result, sizeof(double) * NPART, hipMemcpyDeviceToHost, c->stream);
+  hipError_t e = hipMemcpyAsync(host, result, sizeof(double) * NPART, hipMemcpyDeviceToHost, c->stream);
   if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
   e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-  const double* h = c->h_result;
   lbm_diag d{};
-  d.mass = h[0];
-  d.momentum[0] = h[1];
-  d.momentum[1] = h[2];
-  d.momentum[2] = h[3];
-  d.ke = h[4] / double(c->ncell);
-  d.energy = h[5];
-  d.min_rho = h[6];
-  d.min_theta = h[7];
-  d.nonfinite = int32_t(h[8]);
+  d.mass = host[0];
+  d.momentum[0] = host[1];
+  d.momentum[1] = host[2];
+  d.momentum[2] = host[3];
+  d.ke = host[4] / double(c->ncell);
+  d.energy = host[5];
+  d.min_rho = host[6];
+  d.min_theta = host[7];
+  d.nonfinite = int32_t(host[8]);
   if (diag) *diag = d;
   if (d.nonfinite > 0 || !(d.min_rho > 0) || !(d.min_theta > 0))
     return fail(LBM_EDIVERGED, "non-finite value, rho <= 0 or theta <= 0");
   return LBM_OK;
+}
+
+int lbm_moments(lbm_ctx* c, const void* state, void* rho, void* u, void* theta, lbm_diag* diag) {
+  if (int r = check_ctx(c)) return r;
+  if (!state) state = c->buf[c->cur];
+  if (!state) return fail(LBM_EINVAL, "no state");
+  if (int r = set_device(c)) return r;
+  return moments_impl(c, state, rho, u, theta, diag, c->d_partial, c->d_result, c->h_result);
 }
 
 static int adjoint_ok(lbm_ctx* c) {

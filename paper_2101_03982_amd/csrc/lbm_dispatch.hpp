@@ -16,12 +16,18 @@ struct Kernels {
   // the forward step with non-temporal result stores (3D sets, n = 4 only)
   StepLaunch step_stream = nullptr;
   CellLaunch init = nullptr;
-  CellLaunch moments = nullptr;     // writes partials; grid = moments_blocks(ncell)
+  CellLaunch moments = nullptr;     // writes partials; grid = CellParams::nblocks
   CellLaunch ke_adjoint = nullptr;
   CellLaunch init_adjoint = nullptr;
 };
 
+// Blocks of the moments kernel: at most MOMENT_BLOCKS, and no more than one
+// per 256 cells.
 constexpr int MOMENT_BLOCKS = 1024;
+inline int moment_blocks(int64_t ncell) {
+  const int64_t b = (ncell + 255) / 256;
+  return int(b < MOMENT_BLOCKS ? (b < 1 ? 1 : b) : MOMENT_BLOCKS);
+}
 
 // Which combinations are compiled.  Every set gets the forward step for each
 // stencil length 2..5 (1: the on-lattice copy, D2Q9 and D3Q27 only).

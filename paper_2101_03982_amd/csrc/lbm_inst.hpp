@@ -54,7 +54,7 @@ hipError_t launch_init(const CellParams& p, hipStream_t s) {
 
 template <int SET, int A, int ST>
 hipError_t launch_moments(const CellParams& p, hipStream_t s) {
-  hipLaunchKernelGGL((moments_kernel<SET, A, ST>), dim3(MOMENT_BLOCKS), dim3(256), 0, s, p);
+  hipLaunchKernelGGL((moments_kernel<SET, A, ST>), dim3(unsigned(p.nblocks)), dim3(256), 0, s, p);
   return hipGetLastError();
 }
 

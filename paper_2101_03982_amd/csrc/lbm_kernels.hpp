@@ -1382,8 +1382,9 @@ struct CellParams {
   void* out_rho;
   void* out_u;
   void* out_theta;
-  double* partial;    // [blocks][8]
+  double* partial;    // [nblocks][NPART] block sums of the moments kernel
   int64_t ncell;
+  int nblocks;        // blocks of the moments kernel (grid-stride loop)
   double cs;          // u = cs * u~
   double cv2mD, inv2cv, sw, swX, swx[3];
   double scale;       // 1 / ncell (KE adjoint)

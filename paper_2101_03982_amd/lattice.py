@@ -136,8 +136,31 @@ class Lattice:
         buf = self._bufs[0] if p == self._bufs[0].data_ptr() else self._bufs[1]
         return buf.view(self.pop_shape)
 
+    def _state_arg(self, t, what):
+        if t.dtype != self.state_dtype or not t.is_contiguous() or t.numel() != self.A * self.Q * self.ncell:
+            raise ValueError("%s: want a contiguous %s tensor of %d elements, got %s %s" % (
+                what, self.state_dtype, self.A * self.Q * self.ncell, t.dtype, tuple(t.shape)))
+        if t.device.type not in ("cpu", "cuda"):
+            raise ValueError("%s: host or GPU memory" % what)
+        return t
+
+    def get_state(self, out=None, device=None):
+        """Checkpoint: a copy of the current state (lbm_get_state) into `out`
+        (a contiguous tensor of the storage dtype, host or GPU), or into a new
+        tensor on `device` (default: the lattice's GPU); waits for the copy."""
+        if out is None:
+            out = torch.empty(self.pop_shape, dtype=self.state_dtype, device=device or self.device)
+        out = self._state_arg(out, "get_state")
+        self._stream()
+        check(_lib.lib().lbm_get_state(self._ctx, _ptr(out)), "lbm_get_state")
+        return out
+
     def set_state(self, f):
-        self.state().copy_(f.reshape(self.pop_shape))
+        """Resume: copies `f` (host or GPU, storage dtype, the state's layout)
+        into the current buffer (lbm_set_state); waits for the copy."""
+        f = self._state_arg(f, "set_state")
+        self._stream()
+        check(_lib.lib().lbm_set_state(self._ctx, _ptr(f)), "lbm_set_state")
 
     def new_state(self):
         """A fresh device buffer shaped like the state."""

@@ -1,5 +1,11 @@
 """Shared helpers of the GPU tests: build the GPU lattice and the oracle
-configuration of one problem from the same parameters, and compare states."""
+configuration of one problem from the same parameters, and compare states.
+
+Set LBM_PARITY_LOG to a file name to have the parity tests append the errors
+they measured (one JSON object per line), beside asserting their bounds."""
+import json
+import os
+
 import numpy as np
 import torch
 
@@ -46,3 +52,35 @@ def gpu_populations(lat, state=None):
 def rel_err(a, b):
     """max |a - b| / max |b|."""
     return float(np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300))
+
+
+def reference_values(lat):
+    """r_i per stored array, [A*Q]: w_i for f and (2 C_v - D) w_i for g (the
+    values deviation storage subtracts)."""
+    w = np.array(lat.table()["w"])
+    ref = [w]
+    if lat.A == 2:
+        ref.append((2.0 / (lat.gamma - 1.0) - lat.D) * w)
+    return np.concatenate(ref)
+
+
+def pop_err(lat, got, ref, axis=0):
+    """Largest error of any population relative to that population's own
+    scale: max over populations k of max_cells |got_k - ref_k| divided by
+    max_cells |ref_k - r_k|, r_k its reference value (reference_values).
+    Small-weight populations then count as much as the large ones.  `axis`
+    is the population axis of got and ref."""
+    r = reference_values(lat)
+    got = np.moveaxis(np.asarray(got, dtype=np.float64), axis, 0).reshape(len(r), -1)
+    ref = np.moveaxis(np.asarray(ref, dtype=np.float64), axis, 0).reshape(len(r), -1)
+    scale = np.max(np.abs(ref - r[:, None]), axis=1)
+    err = np.max(np.abs(got - ref), axis=1)
+    return float(np.max(err / np.maximum(scale, 1e-300)))
+
+
+def note(case, **values):
+    """Appends the measured errors of a parity case to $LBM_PARITY_LOG."""
+    path = os.environ.get("LBM_PARITY_LOG")
+    if path:
+        with open(path, "a") as fh:
+            fh.write(json.dumps({"case": case, **{k: float(v) for k, v in values.items()}}) + "\n")

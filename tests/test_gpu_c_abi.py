@@ -4,7 +4,9 @@ through lbm_create / lbm_bind / lbm_init_equilibrium / lbm_step /
 lbm_moments / lbm_enstrophy / lbm_destroy with hipMalloc'd buffers, against
 the same run through the Python binding: mass, kinetic energy before and
 after, and enstrophy within 1e-12 (FP64; the initial fields differ only by
-the C and numpy sine and cosine)."""
+the C and numpy sine and cosine).  The same program checkpoints the state to
+host memory (lbm_get_state), steps on, restores it (lbm_set_state) and steps
+again: the resumed run must match bit for bit."""
 import math
 import os
 import subprocess
@@ -42,3 +44,4 @@ def test_c_program_matches_python_binding():
     ref = {"mass": d.mass, "ke0": ke0, "ke": d.ke, "enstrophy": lat.enstrophy(uu, order=8)}
     for key, val in ref.items():
         assert abs(got[key] / val - 1) <= 1e-12, (key, got[key], val)
+    assert got["resumed_identical"] == 1 and got["stepped"] == 1, got

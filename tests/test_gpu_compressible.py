@@ -7,7 +7,8 @@ and the reduced-precision storage form.
 * Compressible Taylor-Green vortex (CTIC, Sec. 4.3), D3Q45, N = 4, Ma 0.5 and
   1.0: FP64 within 1e-12; total energy conserved on the periodic grid.
 * The paper's own time steps (Table tab:timestepsizes, Ma 0.5 to 2.0, shifts of
-  up to 4 cells per step) on a 16^3 grid: FP64 within 1e-12, FP32 within 1e-5;
+  up to 4 cells per step) on a 16^3 grid: FP64 within 1e-12, FP32 within
+  3e-5 of each population's own scale;
   and at 256^3 to t = 10 at Ma 1.5 and 2.0 (the paper's stability claim):
   positive density and temperature, conserved mass and energy.
 * BF16 / FP16 deviation storage: one step from the equilibrium, each stored
@@ -20,13 +21,31 @@ import pytest
 import torch
 
 import lbm_inputs as W
-from gpu_helpers import gpu_populations, init_both, pair, rel_err
+from gpu_helpers import gpu_populations, init_both, note, pair, pop_err, rel_err
+
+
+def check(lat, got, ref, storage, tol, case):
+    """FP64: relative to the largest population; FP32: relative to each
+    population's own largest deviation from its reference value (w_i for f,
+    (2 C_v - D) w_i for g), so the small-weight populations are held to the
+    same relative bar as the rest populations."""
+    err = rel_err(got, ref) if storage == "f64" else pop_err(lat, got, ref)
+    note(case, err=err)
+    assert err <= tol, (case, err)
 
 pytestmark = pytest.mark.gpu
 
 
+# FP32 bounds of the compressible model, per population (each population's
+# error over its own largest deviation from its reference value): the
+# largest measured is 1.6e-5 (paper time step, Ma 1.0, three steps) and
+# 1.2e-5 (shock-vortex window, ten steps), from FP32 rounding of theta and
+# of the energy sums reaching the populations with the smallest deviations
+F32_COMP = 3e-5
+
+
 @pytest.mark.parametrize("name", ["D2Q19", "D2Q25"])
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", F32_COMP)])
 def test_shock_vortex_parity(orc, name, storage, tol):
     base = W.svi_workload(name, n=512)
     # the same physics on a 140 x 96 window (three x tiles with a ragged tail)
@@ -37,7 +56,7 @@ def test_shock_vortex_parity(orc, name, storage, tol):
     f = init_both(lat, orc, cfg, rho, u, theta)
     lat.step(10)
     f = orc.run(cfg, f, 10)
-    assert rel_err(gpu_populations(lat), f) <= tol
+    check(lat, gpu_populations(lat), f, storage, tol, "svi_%s_%s" % (name, storage))
 
 
 @pytest.mark.parametrize("Ma", [0.5, 1.0])
@@ -57,7 +76,7 @@ def test_compressible_tgv_parity(orc, Ma):
 
 
 @pytest.mark.parametrize("Ma", [0.5, 1.0, 1.5, 2.0])
-@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", 1e-5)])
+@pytest.mark.parametrize("storage,tol", [("f64", 1e-12), ("f32", F32_COMP)])
 def test_compressible_tgv_paper_time_step_parity(orc, Ma, storage, tol):
     """The paper's own D3Q45 runs (Table tab:timestepsizes, Re 400): the
     256^3 run's relaxation time, sound speed and shift in cells (about 4 cells
@@ -70,7 +89,7 @@ def test_compressible_tgv_paper_time_step_parity(orc, Ma, storage, tol):
     f = init_both(lat, orc, cfg, rho, u, theta)
     lat.step(3)
     f = orc.run(cfg, f, 3)
-    assert rel_err(gpu_populations(lat), f) <= tol
+    check(lat, gpu_populations(lat), f, storage, tol, "ctgv_paper_dt_Ma%.1f_%s" % (Ma, storage))
 
 
 def test_moment_fields_match_oracle(orc):
@@ -122,7 +141,8 @@ def test_reduced_precision_one_step(orc, storage, Ma, e64):
 def test_compressible_fp32_parity_ragged(orc, Ma):
     """FP32 f + g storage (eight-wave blocks, one cell per thread) on a grid
     with a ragged tail on every axis, random fields with theta != 1: three
-    steps within 1e-5 of the oracle, relative to the largest population."""
+    steps within 1.5e-5 of the oracle, relative to each population's own
+    largest deviation from its reference value (measured <= 5.8e-6)."""
     base = W.ctgv_workload(n=16, Ma=Ma)
     wl = base.with_(grid=(70, 13, 6))
     lat, cfg = pair(orc, "D3Q45", wl.grid, wl.tau, 4, wl.stencil, "f32", wl.dx, wl.dt, wl.cs,
@@ -131,7 +151,7 @@ def test_compressible_fp32_parity_ragged(orc, Ma):
     f = init_both(lat, orc, cfg, rho, u, theta)
     lat.step(3)
     f = orc.run(cfg, f, 3)
-    assert rel_err(gpu_populations(lat), f) <= 1e-5
+    check(lat, gpu_populations(lat), f, "f32", 1.5e-5, "ctgv_ragged_Ma%.1f" % Ma)
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
@@ -139,9 +159,9 @@ def test_ctgv_full_size_sampled(orc, storage):
     """The precision-form workload at its full size (D3Q45 f + g, 256^3,
     Ma 1.0, the launch configuration the benchmark times): one step from the
     initial condition at 48 sampled cells against the oracle computed cell
-    by cell.  FP32 within 1e-5 of the largest population; BF16 and FP16
-    within three of their ulps of each population's deviation from its
-    reference value (plus 2^-23 for FP16's subnormal range)."""
+    by cell.  FP32 within 1e-5 of each population's largest deviation from
+    its reference value; BF16 and FP16 within three of their ulps of it (plus
+    2^-23 for FP16's subnormal range)."""
     from paper_2101_03982_amd import Lattice
 
     from gpu_helpers import to_dev
@@ -165,7 +185,10 @@ def test_ctgv_full_size_sampled(orc, storage):
     del lat
     torch.cuda.empty_cache()
     if storage == "f32":
-        assert rel_err(got, ref) <= 1e-5, rel_err(got, ref)
+        scale = np.max(np.abs(ref - r), axis=0)
+        err = float(np.max(np.max(np.abs(got - ref), axis=0) / scale))
+        note("ctgv_full_sampled_f32", err=err)
+        assert err <= 1e-5, err
     else:
         scale = np.max(np.abs(ref - r), axis=0, keepdims=True)
         tol = 3 * ULP[storage] * scale + 2.0 ** -23
@@ -201,19 +224,72 @@ def test_high_mach_ctgv_stays_stable(Ma):
     to t = 10 (562 / 841 steps), FP64 and FP32.  Every logged state keeps
     rho > 0 and theta > 0 with no non-finite value; mass and total energy stay
     conserved up to rounding (FP64: 1e-14 per step, a few units of 2^-53 in
-    the global sums; FP32: 1e-6, measured <= 1.5e-7 with the restoration of
-    the rounded constants' mass defect); the kinetic energy decays overall; FP32's
-    kinetic-energy log stays within 1e-5 of FP64's."""
+    the global sums; FP32: 3e-7, measured <= 1.5e-7 with the restoration of
+    the rounded constants' mass defect, 0.6-1.9e-6 without it); the kinetic
+    energy decays overall; FP32's kinetic-energy log stays within 1e-5 of
+    FP64's."""
     wl = W.ctgv_workload(n=256, Ma=Ma, Re=400.0, dt=W.CTGV_PAPER_DT[Ma])
     steps = int(np.ceil(10.0 / wl.dt))
     logs = {st: _ctgv_log(wl, st, steps) for st in ("f64", "f32")}
     drift = {st: (max(abs(d.mass / log[0].mass - 1) for d in log), max(abs(d.energy / log[0].energy - 1) for d in log))
              for st, log in logs.items()}
-    for st, tol in (("f64", 1e-14 * steps), ("f32", 1e-6)):
+    for st, tol in (("f64", 1e-14 * steps), ("f32", 3e-7)):
         log = logs[st]
         assert all(d.nonfinite == 0 and d.min_rho > 0 and d.min_theta > 0 for d in log)
         assert max(drift[st]) <= tol, drift
         assert log[-1].ke < 0.6 * log[0].ke
+    note("high_mach_Ma%.1f" % Ma, mass_f32=drift["f32"][0], energy_f32=drift["f32"][1],
+         mass_f64=drift["f64"][0], energy_f64=drift["f64"][1])
     ke64 = np.array([d.ke for d in logs["f64"]])
     ke32 = np.array([d.ke for d in logs["f32"]])
     assert np.max(np.abs(ke32 / ke64 - 1)) <= 1e-5, float(np.max(np.abs(ke32 / ke64 - 1)))
+
+
+def _svi_run(wl, storage, every=250):
+    """The shock-vortex workload at full length: moments every `every` steps
+    (each call raises on a non-finite value, rho <= 0 or theta <= 0)."""
+    from paper_2101_03982_amd import Lattice
+
+    from gpu_helpers import to_dev
+
+    lat = Lattice(wl.set, wl.grid, wl.tau, wl.order, stencil=wl.stencil, storage=storage, dx=wl.dx, dt=wl.dt,
+                  cs=wl.cs, compressible=True, gamma=wl.gamma, boundary=("extrapolate", "periodic", "periodic"),
+                  device="cuda:0")
+    rho, u, theta = W.svi_fields(wl)
+    lat.init_equilibrium(to_dev(rho, lat.dtype), to_dev(u, lat.dtype), to_dev(theta, lat.dtype))
+    log = [lat.moments(fields=False)[3]]
+    for _ in range(wl.steps // every):
+        lat.step(every)
+        log.append(lat.moments(fields=False)[3])
+    r, uu, th, _ = lat.moments()
+    fields = tuple(x.double().cpu().numpy() for x in (r, uu, th))
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return log, fields
+
+
+@pytest.mark.parametrize("name", ["D2Q19", "D2Q25"])
+def test_shock_vortex_full_run(name):
+    """The shock-vortex workload at its stated size and length (Sec. 4.1,
+    Table tab:setup-2Dvortex): 512^2, N = 4, n = 5, 4000 steps (t' = 8),
+    FP64 and FP32.  Every state logged each 250 steps is finite with rho > 0
+    and theta > 0; the shock and the vortex stay in place of each other (the
+    density jump survives: the largest density is near the Rankine-Hugoniot
+    value); FP32's density, velocity and temperature fields after 4000 steps
+    are within 3e-4 (relative L2) of FP64's (measured for D2Q19: 1.0e-4,
+    1.1e-4, 5.5e-5; FP32 rounding carried through the shock over the run)."""
+    wl = W.svi_workload(name, n=512)
+    runs = {st: _svi_run(wl, st) for st in ("f64", "f32")}
+    r2 = W.rankine_hugoniot(1.2, wl.gamma)[0]
+    for st, (log, _) in runs.items():
+        assert len(log) == wl.steps // 250 + 1
+        assert all(d.nonfinite == 0 and d.min_rho > 0 and d.min_theta > 0 for d in log), st
+    rho64 = runs["f64"][1][0]
+    assert 0.9 * r2 < float(np.max(rho64)) < 1.5 * r2
+    errs = {}
+    for k, what in enumerate(("rho", "u", "theta")):
+        a, b = runs["f32"][1][k], runs["f64"][1][k]
+        errs[what] = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    note("svi_full_%s" % name, **errs)
+    assert max(errs.values()) <= 3e-4, errs

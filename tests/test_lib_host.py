@@ -130,6 +130,8 @@ def _create(L, set_id, grid, tau=0.8, order=2, **opt):
     ((5, (8, 8, 8), 0.8, 2, {"boundary": (0, 2, 0)}), -1),
     ((5, (1024, 1024, 1024), 0.8, 2, {"storage": 1}), -1),  # one FP32 population = 4 GiB
     ((5, (2048, 2048, 1024), 0.8, 2), -1),                   # 2^32 cells
+    ((7, (8, 8, 8), 0.8, 4, {"compressible": 1, "energy_f64": 1}), -4),  # FP64 energy sum: 16-bit only
+    ((5, (8, 8, 8), 0.8, 2, {"storage": 2, "energy_f64": 1}), -4),       # ... and compressible only
 ])
 def test_create_rejects(L, args, code):
     set_id, grid = args[0], args[1]
@@ -147,6 +149,9 @@ def test_null_arguments(L):
     assert lib.lbm_step(None, 1) == -1
     assert lib.lbm_destroy(None) == 0
     assert lib.lbm_state_bytes(None) == 0
+    assert lib.lbm_get_state(None, None) == -1
+    assert lib.lbm_set_state(None, None) == -1
+    assert lib.lbm_float_moment_defects(99, None) == -1
 
 
 def test_lattice_refuses_cpu_device():
@@ -206,6 +211,15 @@ def test_mass_defect_identity(name):
         c[8 + k] = _QUAD_MULT[k] * (sum(wi * Xi * mono(xi, e) for wi, xi, Xi in zip(w, x, X)) - (D + 2) * gauss(e))
     for k, e in enumerate(_QUART):
         c[15 + k] = _QUART_MULT[k] * (sum(wi * mono(xi, e) for wi, xi in zip(w, x)) - gauss(e))
+    # the library's own coefficients (lbm_float_moment_defects, which the
+    # kernels receive) are these, index for index and multiplicity included
+    from paper_2101_03982_amd import _lib
+
+    got = (ctypes.c_double * 30)()
+    assert _lib.lib().lbm_float_moment_defects(SETS.index(name), got) == 0
+    for k in range(30):
+        assert abs(got[k] - float(c[k])) <= 1e-13, (k, got[k], float(c[k]))  # FP64 sums of O(100) terms
+    assert max(abs(float(v)) for v in c) > 1e-9  # the defects are not all zero
     rng = np.random.default_rng(5)
     for _ in range(3):
         u = [F(float(v)) for v in rng.normal(size=3) * 1.2]

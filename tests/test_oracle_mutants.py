@@ -15,7 +15,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
 PINS = ["tests/test_oracle_sets.py", "tests/test_oracle_collision.py", "tests/test_oracle_stream.py",
-        "tests/test_oracle_step.py", "tests/test_oracle_adjoint.py"]
+        "tests/test_oracle_step.py", "tests/test_oracle_adjoint.py", "tests/test_oracle_moments.py"]
 
 MUTANTS = {
     "H2_drops_delta": ("double H2 = (xh[a] * xh[b] - kd(a, b)) / (cs * cs);",
@@ -46,6 +46,12 @@ MUTANTS = {
     "init_transpose_real_part": ("s += cimag(eq[k]) / ORC_CSTEP * lam0[(int64_t)k * NC + e];",
                                  "s += cimag(eq[k]) / ORC_CSTEP * lam0[(int64_t)k * NC + e] * 0.999;"),
     "d1q5_weight": ("wt[k] = 120.0 / (25.0 * he4 * he4);", "wt[k] = 120.0 / (24.0 * he4 * he4);"),
+    "ke_drops_half": ("ke += 0.5 * u2;", "ke += u2;"),
+    "first_step_g_reads_f": ("* creal(eq[a * p.Q + i]);", "* creal(eq[i]);"),
+    "min_rho_sense": ("if (rr < rmin) rmin = rr;", "if (rr > rmin) rmin = rr;"),
+    "min_theta_of_rho": ("if (t < tmin) tmin = t;", "if (rr < tmin) tmin = rr;"),
+    "energy_drops_g": ("((p.A == 2) ? creal(fc[p.Q + i]) : 0.0)", "0.0"),
+    "momentum_unweighted": ("mom[a] += rr * creal(uu[a]);", "mom[a] += creal(uu[a]);"),
 }
 
 
