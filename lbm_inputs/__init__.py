@@ -64,6 +64,7 @@ class Workload:
     bc: tuple = (PERIODIC, PERIODIC, PERIODIC)
     storage: str = "f64"
     log_every: int = 50
+    support: str = "uniform"  # node placement: "uniform", or "glc" (cells of `stencil` GLC points)
 
     @property
     def D(self):
@@ -94,12 +95,38 @@ def courant_dt(dx: float, cs: float, sets, courant: float = 0.5) -> float:
     return courant * dx / vmax
 
 
-def _grid_coords(shape, dx):
+def glc_nodes(n: int, p: int, dx: float):
+    """Coordinates of the n nodes of a periodic axis divided into n / p cells
+    of p + 1 Gauss-Lobatto-Chebyshev support points (the paper's cell-wise
+    support, Sec. 3); neighbouring cells share their end points, and a cell
+    is p dx wide, so the mean spacing is dx.  Node j = c p + k lies at
+    (c + (1 - cos(pi k / p)) / 2) p dx."""
+    if n % p:
+        raise ValueError("%d nodes do not make whole cells of %d intervals" % (n, p))
+    j = np.arange(n)
+    c, k = j // p, j % p
+    return (c + 0.5 * (1.0 - np.cos(np.pi * k / p))) * p * dx
+
+
+def _axis(n, dx, glc_p=None):
+    if glc_p:
+        return glc_nodes(n, glc_p, dx)
+    return np.arange(n, dtype=np.float64) * dx
+
+
+def _grid_coords(shape, dx, glc_p=None):
+    """Node coordinates (Z, Y, X) of a [nz][ny][nx] grid: uniform spacing dx,
+    or Gauss-Lobatto-Chebyshev cells of glc_p intervals along every axis
+    with more than one node."""
     nz, ny, nx = shape
-    z = np.arange(nz, dtype=np.float64) * dx
-    y = np.arange(ny, dtype=np.float64) * dx
-    x = np.arange(nx, dtype=np.float64) * dx
+    z = _axis(nz, dx, glc_p if nz > 1 else None)
+    y = _axis(ny, dx, glc_p)
+    x = _axis(nx, dx, glc_p)
     return np.meshgrid(z, y, x, indexing="ij")
+
+
+def _coords(wl):
+    return _grid_coords(wl.shape, wl.dx, wl.stencil - 1 if wl.support == "glc" else None)
 
 
 # ---------------------------------------------------------------------------
@@ -126,7 +153,7 @@ def tgv2d_fields(wl: Workload, noise: float = 1e-6, seed: int = 0):
     nx, ny, _ = wl.grid
     u0 = 0.05 * wl.cs
     k = 2.0 * math.pi / (nx * wl.dx)
-    _, Y, X = _grid_coords((1, ny, nx), wl.dx)
+    _, Y, X = _coords(wl)
     ux = u0 * np.sin(k * X) * np.cos(k * Y)
     uy = -u0 * np.cos(k * X) * np.sin(k * Y)
     rho = 1.0 + (u0 * u0 / (4.0 * wl.cs * wl.cs)) * (np.cos(2 * k * X) + np.cos(2 * k * Y))
@@ -153,10 +180,13 @@ TGV3D_SETS = ("D3Q13", "D3Q21", "D3V27", "D3Q27")
 
 def tgv3d_workload(set_: str, n: int = 128, steps: int = 2000, Ma: float = 0.1, Re: float = 1600.0,
                    storage: str = "f32", stencil: int = 4, courant_sets=TGV3D_SETS,
-                   order: int | None = None) -> Workload:
+                   order: int | None = None, support: str = "uniform") -> Workload:
     """Domain [0, 2 pi)^3 with n^3 nodes, u0 = 1, L = 1, c_s = 1/Ma, nu = 1/Re
-    (Sec. 4.2); one time step for all sets in ``courant_sets`` at Courant 0.5;
-    N = 2, except N = 3 for D3V27 (Sec. 4.2)."""
+    (Sec. 4.2); one time step for all sets in ``courant_sets`` at Courant 0.5
+    (of the mean node spacing); N = 2, except N = 3 for D3V27 (Sec. 4.2).
+    support="glc": the paper's own discretization, n/p cells of p + 1
+    Gauss-Lobatto-Chebyshev points per axis with p = stencil - 1 (the paper's
+    128^3 points are 32^3 cells with p = 4, Sec. 4.2)."""
     dx = 2.0 * math.pi / n
     cs = 1.0 / Ma
     dt = courant_dt(dx, cs, courant_sets)
@@ -164,7 +194,7 @@ def tgv3d_workload(set_: str, n: int = 128, steps: int = 2000, Ma: float = 0.1, 
     if order is None:
         order = 3 if set_ == "D3V27" else 2
     return Workload("tgv3d", set_, (n, n, n), dx, dt, cs, relaxation_time(nu, cs, dt), order, stencil, steps,
-                    storage=storage)
+                    storage=storage, support=support)
 
 
 def tgv3d_pressure(X, Y, Z):
@@ -177,7 +207,7 @@ def tgv3d_pressure(X, Y, Z):
 def tgv3d_fields(wl: Workload, sigma: float = 0.0, seed: int = 1):
     """u = (sin x cos y cos z, -cos x sin y cos z, 0), rho = 1 + p'/c_s^2, plus an
     optional N(0, sigma^2) perturbation per component from ``default_rng(seed)``."""
-    Z, Y, X = _grid_coords(wl.shape, wl.dx)
+    Z, Y, X = _coords(wl)
     u = np.stack([np.sin(X) * np.cos(Y) * np.cos(Z), -np.cos(X) * np.sin(Y) * np.cos(Z), np.zeros_like(X)])
     rho = 1.0 + tgv3d_pressure(X, Y, Z) / (wl.cs * wl.cs)
     if sigma:
@@ -230,7 +260,7 @@ def ctgv_fields(wl: Workload):
     """Constant-temperature initial condition (Sec. 4.3 with C = 1):
     rho = 1 + (1/16)(cos 2x + cos 2y)(cos 2z + 2), theta = 1, velocity of the
     Taylor-Green vortex."""
-    Z, Y, X = _grid_coords(wl.shape, wl.dx)
+    Z, Y, X = _coords(wl)
     u = np.stack([np.sin(X) * np.cos(Y) * np.cos(Z), -np.cos(X) * np.sin(Y) * np.cos(Z), np.zeros_like(X)])
     rho = 1.0 + tgv3d_pressure(X, Y, Z)
     return rho, u, np.ones_like(rho)

@@ -51,6 +51,11 @@
 
 enum { ORC_D2Q9 = 0, ORC_D2Q19, ORC_D2Q25, ORC_D3Q13, ORC_D3Q21, ORC_D3Q27, ORC_D3V27, ORC_D3Q45, ORC_NSETS };
 enum { ORC_PERIODIC = 0, ORC_EXTRAPOLATE = 1 };
+/* Streaming support: a uniform grid with an n-node Lagrange stencil around
+ * the departure point, or the paper's own cell-wise form: cells of p + 1
+ * Gauss-Lobatto-Chebyshev support points (p = stencil - 1), neighbouring cells
+ * sharing their end points. */
+enum { ORC_UNIFORM = 0, ORC_GLC = 1 };
 
 /* Configuration handed in from Python (ctypes mirror in oracle/oracle.py). */
 typedef struct {
@@ -60,7 +65,7 @@ typedef struct {
   int32_t compressible; /* 0: f only, theta = 1; 1: f and g */
   int64_t nx, ny, nz;   /* grid (nz = 1 in 2D) */
   int32_t bc[3];        /* per axis: ORC_PERIODIC or ORC_EXTRAPOLATE */
-  int32_t pad;
+  int32_t kind;         /* ORC_UNIFORM or ORC_GLC (streaming support, below) */
   double dx, dt;        /* grid spacing and time step */
   double cs;            /* target speed of sound (<= 0: the table's own) */
   double tau;           /* relaxation time (at rho theta = 1 when compressible) */
@@ -316,6 +321,15 @@ static int setup(const orc_cfg *c, orc_prob *p) {
   p->n[0] = c->nx; p->n[1] = c->ny; p->n[2] = (p->D == 3) ? c->nz : 1;
   p->ncell = p->n[0] * p->n[1] * p->n[2];
   if (c->order < 0 || c->order > 4 || c->stencil < 1) return -1;
+  if (c->kind == ORC_GLC) {
+    /* every axis is a whole number of periodic cells of p nodes */
+    const int pp = c->stencil - 1;
+    if (pp < 1 || pp > 7) return -1;
+    for (int a = 0; a < p->D; ++a)
+      if (p->n[a] % pp != 0 || c->bc[a] != ORC_PERIODIC) return -1;
+  } else if (c->kind != ORC_UNIFORM) {
+    return -1;
+  }
   return 0;
 }
 
@@ -380,19 +394,64 @@ static inline double shift_of(const orc_prob *p, int i, int axis) {
   return p->t.xi[i][axis] * p->c.dt / p->c.dx;
 }
 
+/* Gauss-Lobatto-Chebyshev support point m of a cell of order pp, in cell
+ * units: the extrema of the Chebyshev polynomial T_pp mapped onto [0, 1]
+ * (Sec. 3: the support points of the paper's cell-wise interpolation). */
+static inline double glc_point(int m, int pp) {
+  const double pi = 3.14159265358979323846;
+  return 0.5 * (1.0 - cos(pi * (double)m / (double)pp));
+}
+
+/* Cell-wise streaming (Sec. 3, eq. sl_streaming): node j is support point k
+ * of cell c (j = c pp + k; the cell's last point is the next cell's first).
+ * Its departure point lies s nodes' mean spacing upstream, i.e. s / pp cells,
+ * at r = glc_point(k) - s / pp cells from the start of cell c.  The cell that
+ * holds it is c + floor(r); the value there is the interpolation polynomial
+ * of that cell, sum_t psi_t(eta) f(node t of the cell), with eta the
+ * departure point's coordinate in the cell and psi_t the Lagrange
+ * polynomials through the cell's pp + 1 support points. */
+static void stencil_glc(int64_t j, double s, int pp, int64_t *nodes, double *L) {
+  int64_t c = j / pp, k = j % pp;
+  if (k < 0) { k += pp; c -= 1; }
+  const double r = glc_point((int)k, pp) - s / (double)pp;
+  const double d = floor(r);
+  const double eta = r - d;
+  const int64_t first = (c + (int64_t)d) * pp;
+  for (int t = 0; t <= pp; ++t) nodes[t] = first + t;
+  for (int t = 0; t <= pp; ++t) {
+    double num = 1.0, den = 1.0;
+    for (int m = 0; m <= pp; ++m) {
+      if (m == t) continue;
+      num *= eta - glc_point(m, pp);
+      den *= glc_point(t, pp) - glc_point(m, pp);
+    }
+    L[t] = num / den;
+  }
+}
+
+/* The nodes and weights of population i's interpolation along `axis` for
+ * arrival node j, for either streaming support; returns the node count. */
+static int axis_stencil(const orc_prob *p, int i, int axis, int64_t j, int64_t *nodes, double *L) {
+  const int n = p->c.stencil;
+  if (p->c.kind == ORC_GLC) {
+    stencil_glc(j, shift_of(p, i, axis), n - 1, nodes, L);
+    return n;
+  }
+  stencil_1d(j, shift_of(p, i, axis), n, nodes, L);
+  return n;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Streaming (Sec. 3, eq. sl_streaming): full tensor-product sum             */
 /* ------------------------------------------------------------------------ */
 
 static double interp_at(const orc_prob *p, const double *fi, int i, const int64_t x[3]) {
-  const int n = p->c.stencil;
   int64_t nodes[3][8];
   double L[3][8];
   int na[3] = {1, 1, 1};
   for (int a = 0; a < 3; ++a) {
     if (a < p->D) {
-      stencil_1d(x[a], shift_of(p, i, a), n, nodes[a], L[a]);
-      na[a] = n;
+      na[a] = axis_stencil(p, i, a, x[a], nodes[a], L[a]);
     } else {
       nodes[a][0] = 0;
       L[a][0] = 1.0;
@@ -433,7 +492,6 @@ int orc_stream_transpose(const orc_cfg *c, const double *mu, double *lam) {
   orc_prob p;
   if (setup(c, &p)) return -1;
   const int64_t NC = p.ncell;
-  const int n = p.c.stencil;
   memset(lam, 0, sizeof(double) * (size_t)(p.A * p.Q) * (size_t)NC);
   for (int a = 0; a < p.A; ++a)
     for (int i = 0; i < p.Q; ++i) {
@@ -447,8 +505,7 @@ int orc_stream_transpose(const orc_cfg *c, const double *mu, double *lam) {
         int na[3] = {1, 1, 1};
         for (int ax = 0; ax < 3; ++ax) {
           if (ax < p.D) {
-            stencil_1d(x[ax], shift_of(&p, i, ax), n, nodes[ax], L[ax]);
-            na[ax] = n;
+            na[ax] = axis_stencil(&p, i, ax, x[ax], nodes[ax], L[ax]);
           } else {
             nodes[ax][0] = 0;
             L[ax][0] = 1.0;
@@ -714,7 +771,7 @@ int orc_first_step_at(const orc_cfg *c, const double *rho, const double *u, cons
   orc_prob p;
   if (setup(c, &p)) return -1;
   const int64_t NC = p.ncell;
-  const int n = p.c.stencil, AQ = p.A * p.Q;
+  const int AQ = p.A * p.Q;
 #pragma omp parallel for schedule(dynamic)
   for (int64_t s = 0; s < ncells; ++s) {
     int64_t x[3];
@@ -727,8 +784,7 @@ int orc_first_step_at(const orc_cfg *c, const double *rho, const double *u, cons
         int na[3] = {1, 1, 1};
         for (int ax = 0; ax < 3; ++ax) {
           if (ax < p.D) {
-            stencil_1d(x[ax], shift_of(&p, i, ax), n, nodes[ax], L[ax]);
-            na[ax] = n;
+            na[ax] = axis_stencil(&p, i, ax, x[ax], nodes[ax], L[ax]);
           } else {
             nodes[ax][0] = 0;
             L[ax][0] = 1.0;

@@ -24,6 +24,11 @@ _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 SETS = ["D2Q9", "D2Q19", "D2Q25", "D3Q13", "D3Q21", "D3Q27", "D3V27", "D3Q45"]
 PERIODIC, EXTRAPOLATE = 0, 1
+# streaming support: uniform grid with an n-node Lagrange stencil, or the
+# paper's cell-wise interpolation on Gauss-Lobatto-Chebyshev points
+# (cells of p = stencil - 1 intervals; periodic axes whose extents are
+# multiples of p)
+KINDS = ("uniform", "glc")
 
 GCC_FLAGS = ["-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11"]
 
@@ -47,7 +52,7 @@ class _Cfg(ctypes.Structure):
         ("ny", ctypes.c_int64),
         ("nz", ctypes.c_int64),
         ("bc", ctypes.c_int32 * 3),
-        ("pad", ctypes.c_int32),
+        ("kind", ctypes.c_int32),
         ("dx", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("cs", ctypes.c_double),
@@ -93,6 +98,7 @@ class Config:
     compressible: bool = False
     gamma: float = 1.4
     bc: tuple = (PERIODIC, PERIODIC, PERIODIC)
+    kind: str = "uniform"
     _c: _Cfg = field(default=None, repr=False)
 
     def __post_init__(self):
@@ -105,6 +111,7 @@ class Config:
         c.nx, c.ny, c.nz = int(nx), int(ny), int(nz)
         for a in range(3):
             c.bc[a] = int(self.bc[a])
+        c.kind = KINDS.index(self.kind)
         c.dx, c.dt, c.cs, c.tau, c.gamma = (float(self.dx), float(self.dt), float(self.cs),
                                             float(self.tau), float(self.gamma))
         self._c = c

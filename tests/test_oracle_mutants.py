@@ -15,7 +15,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
 PINS = ["tests/test_oracle_sets.py", "tests/test_oracle_collision.py", "tests/test_oracle_stream.py",
-        "tests/test_oracle_step.py", "tests/test_oracle_adjoint.py", "tests/test_oracle_moments.py"]
+        "tests/test_oracle_step.py", "tests/test_oracle_adjoint.py", "tests/test_oracle_moments.py",
+        "tests/test_oracle_glc.py"]
 
 MUTANTS = {
     "H2_drops_delta": ("double H2 = (xh[a] * xh[b] - kd(a, b)) / (cs * cs);",
@@ -52,6 +53,11 @@ MUTANTS = {
     "min_theta_of_rho": ("if (t < tmin) tmin = t;", "if (rr < tmin) tmin = rr;"),
     "energy_drops_g": ("((p.A == 2) ? creal(fc[p.Q + i]) : 0.0)", "0.0"),
     "momentum_unweighted": ("mom[a] += rr * creal(uu[a]);", "mom[a] += creal(uu[a]);"),
+    "glc_points_uniform": ("return 0.5 * (1.0 - cos(pi * (double)m / (double)pp));", "return (double)m / (double)pp;"),
+    "glc_shift_sign": ("const double r = glc_point((int)k, pp) - s / (double)pp;",
+                       "const double r = glc_point((int)k, pp) + s / (double)pp;"),
+    "glc_cell_ceil": ("const double d = floor(r);", "const double d = ceil(r);"),
+    "glc_shift_in_nodes": ("- s / (double)pp;", "- s;"),
 }
 
 
