@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--only", default=None,
-                    help="run one leg alone and print its JSON (precision, svi, svi2048, adjoint, large_grid); "
+                    help="run one leg alone and print its JSON (precision, svi, svi2048, adjoint, large_grid, glc); "
                          "with --precision-steps and --storages it is the profiling target of one kernel family")
     ap.add_argument("--storages", default="f64,f32,bf16,f16", help="storages of the precision leg")
     ap.add_argument("--machs", default="0.5,1.0", help="Mach numbers of the precision leg")
@@ -438,6 +438,35 @@ def on_lattice_ratio(n=128):
     return out
 
 
+def glc_throughput(sets=("D3Q13", "D3Q21", "D3V27", "D3Q27"), n=128):
+    """The paper's own streaming support on the Taylor-Green workload's grid:
+    32^3 cells of p = 4 Gauss-Lobatto-Chebyshev points (128^3 nodes, Sec.
+    4.2), FP32, single-launch time per set beside the uniform tricubic step."""
+    import torch
+
+    import lbm_inputs as W
+    from paper_2101_03982_amd import Lattice
+
+    out = {}
+    for s in sets:
+        wl = W.tgv3d_workload(s, n=n, stencil=5, support="glc")
+        lat = Lattice(s, wl.grid, wl.tau, wl.order, stencil=5, storage="f32", dx=wl.dx, dt=wl.dt, cs=wl.cs,
+                      support="glc", device="cuda:0")
+        rho, u, _ = W.tgv3d_fields(wl)
+        lat.init_equilibrium(torch.from_numpy(rho).to("cuda:0", torch.float32),
+                             torch.from_numpy(u).to("cuda:0", torch.float32))
+        ms = kernel_time(lat)
+        gbs = 2 * lat.Q * 4 * wl.ncell / (ms * 1e-3) / 1e9
+        out[s] = {"kernel_ms": ms, "mlups": wl.ncell / (ms * 1e-3) / 1e6, "achieved_GBs": gbs,
+                  "hbm_frac": gbs / HBM_PEAK_GBS}
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    out["workload"] = ("3D Taylor-Green vortex %d^3 nodes = %d^3 cells of p = 4 Gauss-Lobatto-Chebyshev points, "
+                       "FP32, cell-wise streaming" % (n, n // 4))
+    return out
+
+
 def svi_throughput(n=512):
     """Shock-vortex workload (D2Q19 / D2Q25, f + g, N = 4, n = 5, extrapolating
     in x) at n^2 (512^2, the workload's size, whose two buffers fit in the
@@ -481,6 +510,7 @@ def run_only(a):
         "svi2048": lambda: svi_throughput(2048),
         "adjoint": adjoint_cost,
         "large_grid": large_grid,
+        "glc": glc_throughput,
     }
     if a.only not in legs:
         print("unknown leg %r (one of %s)" % (a.only, ", ".join(sorted(legs))), file=sys.stderr)
@@ -637,6 +667,7 @@ def main():
         out["large_grid"] = large_grid()
         out["svi"] = svi_throughput()
         out["svi_2048"] = svi_throughput(2048)
+        out["glc"] = glc_throughput()
         out["on_lattice"] = on_lattice_ratio()
         out["dissipation"] = dissipation(sets)
         torch.cuda.empty_cache()

@@ -77,6 +77,23 @@ typedef enum lbm_storage {
   LBM_F16DEV = 3    /* IEEE half deviations f - r, float arithmetic */
 } lbm_storage;
 
+/* Streaming support (Sec. 3, eq. sl_streaming).  LBM_UNIFORM: equally spaced
+ * nodes, a stencil of `stencil` Lagrange nodes around every departure point.
+ * LBM_GLC: the paper's own form: every axis is cut into cells of p + 1
+ * Gauss-Lobatto-Chebyshev support points, p = stencil - 1, at
+ * (c + (1 - cos(pi k / p)) / 2) p dx for node c p + k (neighbouring cells
+ * share their end points; dx is the mean node spacing); each node's
+ * departure point is interpolated with the polynomial through the points of
+ * the cell that holds it.  Built for p = 4 (stencil 5), the weakly
+ * compressible model with D2Q9, D3Q13, D3Q21, D3Q27, D3V27 at their
+ * workload orders (N = 2; N = 3 for D3V27), LBM_F64 / LBM_F32, periodic axes
+ * whose extents are multiples of p, forward steps (no adjoint);
+ * LBM_EUNSUPPORTED otherwise. */
+typedef enum lbm_support {
+  LBM_UNIFORM = 0,
+  LBM_GLC = 1
+} lbm_support;
+
 typedef enum lbm_boundary {
   LBM_PERIODIC = 0,     /* node indices wrap around */
   LBM_EXTRAPOLATE = 1   /* zeroth-order extrapolation: indices clamp to the edge */
@@ -84,13 +101,13 @@ typedef enum lbm_boundary {
 
 typedef struct lbm_options {
   int32_t storage;       /* lbm_storage */
-  int32_t stencil;       /* Lagrange nodes per axis n, 1..5 */
+  int32_t stencil;       /* Lagrange nodes per axis n, 1..5 (LBM_GLC: p + 1 points per cell edge) */
   int32_t compressible;  /* 0: f only, theta = 1; 1: f and g (Sec. 3) */
   int32_t boundary[3];   /* lbm_boundary per axis x, y, z */
   int32_t energy_f64;    /* 16-bit storage, compressible: sum the energy moment in FP64
                             (LBM_EUNSUPPORTED with any other storage or model) */
-  int32_t reserved;
-  double dx;             /* grid spacing (> 0) */
+  int32_t support;       /* lbm_support: where the nodes sit and how streaming interpolates */
+  double dx;             /* grid spacing (> 0; LBM_GLC: the mean node spacing, cell width p dx) */
   double dt;             /* time step (> 0) */
   double cs;             /* speed of sound the set is scaled to; <= 0: the table's own */
   double gamma;          /* heat capacity ratio (compressible; C_v = 1/(gamma - 1)) */

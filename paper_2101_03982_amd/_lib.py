@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 SETS = ("D2Q9", "D2Q19", "D2Q25", "D3Q13", "D3Q21", "D3Q27", "D3V27", "D3Q45")
 STORAGES = ("f64", "f32", "bf16", "f16")
 BOUNDARIES = ("periodic", "extrapolate")
+SUPPORTS = ("uniform", "glc")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSUPPORTED, LBM_EDIVERGED = 0, -1, -2, -3, -4, -5
 
@@ -25,7 +26,7 @@ class Options(ctypes.Structure):
         ("compressible", ctypes.c_int32),
         ("boundary", ctypes.c_int32 * 3),
         ("energy_f64", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("support", ctypes.c_int32),
         ("dx", ctypes.c_double),
         ("dt", ctypes.c_double),
         ("cs", ctypes.c_double),

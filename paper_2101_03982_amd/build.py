@@ -54,6 +54,16 @@ def unit_flags(path):
     return []
 
 
+GLC_SETS = ("D2Q9", "D3Q13", "D3Q21", "D3Q27", "D3V27")
+
+
+def _unit(s, st, ns):
+    return ('#include "lbm_inst.hpp"\n'
+            "namespace lbm {\n"
+            "template bool find_kernels_part<%s, %s, %s>(int, int, Kernels*);\n"
+            "}  // namespace lbm\n" % (s, st, ns))
+
+
 def parts():
     """(name, source text) of every kernel-table unit."""
     out = []
@@ -65,11 +75,10 @@ def parts():
                 if ns == 1 and s not in ("D2Q9", "D3Q27"):
                     continue
                 name = "part_%s_%s_%d" % (s, st[3:].lower(), ns)
-                src = ('#include "lbm_inst.hpp"\n'
-                       "namespace lbm {\n"
-                       "template bool find_kernels_part<%s, %s, %d>(int, int, Kernels*);\n"
-                       "}  // namespace lbm\n" % (s, st, ns))
-                out.append((name, src))
+                out.append((name, _unit(s, st, str(ns))))
+            # the cell-wise Gauss-Lobatto-Chebyshev support, p = 4
+            if s in GLC_SETS and st in ("ST_F64", "ST_F32"):
+                out.append(("part_%s_%s_glc4" % (s, st[3:].lower()), _unit(s, st, "GLC_P4")))
     return out
 
 

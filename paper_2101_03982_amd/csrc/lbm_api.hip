@@ -103,6 +103,9 @@ struct lbm_ctx {
   void* d_wts = nullptr;
   int* d_off_t = nullptr;
   void* d_wts_t = nullptr;
+  void* d_glcx = nullptr;   // cell-wise support: compact per-phase entries [Q][3][p][8]
+  int glc_p = 0;            // cell-wise support: cell order p (0: uniform support)
+  int cus = 0;              // compute units of the device
   double* d_partial = nullptr;
   double* d_result = nullptr;
   double* h_result = nullptr;
@@ -230,6 +233,8 @@ KParams base_params(const lbm_ctx* c) {
   p.wts = c->d_wts;
   p.off_t = c->d_off_t;
   p.wts_t = c->d_wts_t;
+  p.glcx = c->d_glcx;
+  p.cus = c->cus;
   for (int a = 0; a < 3; ++a) {
     p.n[a] = int(c->n[a]);
     p.bc[a] = c->bc[a];
@@ -266,6 +271,28 @@ CellParams base_cell(const lbm_ctx* c) {
 // Host stencil tables for the kernels: offsets [Q][3] and weights [Q][3][ns]
 // in the compute type; `transpose` gives the stencil of S^T (mirrored offsets,
 // reversed weights).
+// Cell-wise support (glc_p > 0): offsets [Q][3] (the window's start, dmin p
+// nodes from the arrival node's cell), window weights w [Q][3][p][2p + 1] and
+// compact entries x [Q][3][p][8] (glc_axis); axes along which a population
+// does not move keep offset 0 and are never interpolated.  Returns false if
+// some population's phases span more than two cells.
+bool build_glc_tables(const lbm_ctx* c, std::vector<int>& off, std::vector<double>& w, std::vector<double>& x) {
+  const SetTable t = set_table(c->set);
+  const int p = c->glc_p, win = 2 * p + 1;
+  off.assign(size_t(c->Q) * 3, 0);
+  w.assign(size_t(c->Q) * 3 * p * win, 0.0);
+  x.assign(size_t(c->Q) * 3 * p * 8, 0.0);
+  const int bits = compute_is_f64(c) ? 53 : 24;
+  for (int i = 0; i < c->Q; ++i)
+    for (int a = 0; a < c->D; ++a) {
+      if (t.xh[i][a] == 0.0) continue;
+      const double s = t.xh[i][a] * c->cs * c->dt / c->dx;
+      if (!glc_axis(s, p, bits, &off[i * 3 + a], &w[(size_t(i) * 3 + a) * p * win], &x[(size_t(i) * 3 + a) * p * 8]))
+        return false;
+    }
+  return true;
+}
+
 void build_tables(const lbm_ctx* c, bool transpose, std::vector<int>& off, std::vector<double>& w) {
   const SetTable t = set_table(c->set);
   const int ns = c->ns;
@@ -308,6 +335,21 @@ void build_tables(const lbm_ctx* c, bool transpose, std::vector<int>& off, std::
 // for arrival nodes 0 <= j < N, so every offset o needs -N <= o and
 // o + n <= N + 1.
 int check_reach(const lbm_ctx* c) {
+  if (c->glc_p) {
+    // the window of a tile runs from its first cell's start + dmin p to its last
+    // cell's start + (dmin + 2) p; the kernels wrap indices in [-N, 2N)
+    std::vector<int> off;
+    std::vector<double> w, x;
+    if (!build_glc_tables(c, off, w, x)) return fail(LBM_EINVAL, "a population's phases span more than two cells");
+    for (int i = 0; i < c->Q; ++i)
+      for (int a = 0; a < c->D; ++a) {
+        const int64_t o = off[i * 3 + a], N = c->n[a];
+        if (o < -N || o + 2 * c->glc_p > N)
+          return fail(LBM_EINVAL, "grid extent " + std::to_string(N) + " along axis " + std::to_string(a) +
+                                      " cannot hold a cell-wise window at offset " + std::to_string(o));
+      }
+    return LBM_OK;
+  }
   for (int tr = 0; tr < 2; ++tr) {
     std::vector<int> off;
     std::vector<double> w;
@@ -324,7 +366,33 @@ int check_reach(const lbm_ctx* c) {
   return LBM_OK;
 }
 
+// Copies a table of doubles to a new device buffer in the compute type.
+int upload_reals(const lbm_ctx* c, const std::vector<double>& v, void** dst, const char* what) {
+  const size_t el = compute_is_f64(c) ? sizeof(double) : sizeof(float);
+  hipError_t e = hipMalloc(dst, v.size() * el);
+  if (e != hipSuccess) return fail(LBM_ENOMEM, std::string("hipMalloc ") + what);
+  if (compute_is_f64(c)) {
+    e = hipMemcpy(*dst, v.data(), v.size() * el, hipMemcpyHostToDevice);
+  } else {
+    std::vector<float> f(v.begin(), v.end());
+    e = hipMemcpy(*dst, f.data(), f.size() * el, hipMemcpyHostToDevice);
+  }
+  if (e != hipSuccess) return hip_fail(e, what);
+  return LBM_OK;
+}
+
 int upload_tables(lbm_ctx* c) {
+  if (c->glc_p) {
+    std::vector<int> off;
+    std::vector<double> w, x;
+    if (!build_glc_tables(c, off, w, x)) return fail(LBM_EINVAL, "a population's phases span more than two cells");
+    hipError_t e = hipMalloc(&c->d_off, off.size() * sizeof(int));
+    if (e != hipSuccess) return fail(LBM_ENOMEM, "hipMalloc offsets");
+    e = hipMemcpy(c->d_off, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy offsets");
+    if (int r = upload_reals(c, w, &c->d_wts, "window weights")) return r;
+    return upload_reals(c, x, &c->d_glcx, "compact weights");
+  }
   for (int tr = 0; tr < 2; ++tr) {
     std::vector<int> off;
     std::vector<double> w;
@@ -355,6 +423,7 @@ void release(lbm_ctx* c) {
   if (c->d_wts) (void)hipFree(c->d_wts);
   if (c->d_off_t) (void)hipFree(c->d_off_t);
   if (c->d_wts_t) (void)hipFree(c->d_wts_t);
+  if (c->d_glcx) (void)hipFree(c->d_glcx);
   if (c->d_partial) (void)hipFree(c->d_partial);
   if (c->d_result) (void)hipFree(c->d_result);
   if (c->h_result) (void)hipHostFree(c->h_result);
@@ -511,9 +580,19 @@ int lbm_create(lbm_ctx** out, int32_t set, const int64_t grid[3], double tau, in
       const double s = t.xh[i][a] * c->cs * c->dt / c->dx;
       if (s != std::nearbyint(s)) integral = false;
     }
-  // kernel stencil length: on-lattice sets with a copy kernel use one node
+  // kernel stencil length: on-lattice sets with a copy kernel use one node;
+  // the cell-wise support has its own kernels (p = stencil - 1)
   const bool has_copy = (set == LBM_D2Q9 || set == LBM_D3Q27);
-  if ((integral || c->ns_user == 1) && has_copy) {
+  if (o.support != LBM_UNIFORM && o.support != LBM_GLC) return bad(LBM_EINVAL, "unknown streaming support");
+  if (o.support == LBM_GLC) {
+    c->glc_p = c->ns_user - 1;
+    if (c->glc_p != 4) return bad(LBM_EUNSUPPORTED, "cell-wise support is built for p = 4 (stencil 5)");
+    for (int a = 0; a < c->D; ++a) {
+      if (c->bc[a] != LBM_PERIODIC) return bad(LBM_EUNSUPPORTED, "cell-wise support needs periodic axes");
+      if (c->n[a] % c->glc_p) return bad(LBM_EINVAL, "cell-wise support: extents must be multiples of p");
+    }
+    c->ns = GLC_BASE + c->glc_p;
+  } else if ((integral || c->ns_user == 1) && has_copy) {
     c->ns = 1;
     c->onlattice = integral;
   } else if (c->ns_user == 1) {
@@ -538,6 +617,7 @@ int lbm_create(lbm_ctx** out, int32_t set, const int64_t grid[3], double tau, in
   if (check_reach(c) != LBM_OK) return bad(LBM_EINVAL, g_last_error);
 
   hipError_t e = hipGetDevice(&c->device);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device);
   if (e != hipSuccess) {
     int r = hip_fail(e, "hipGetDevice");
     release(c);
@@ -836,6 +916,7 @@ static bool find_st(int ns, int order, int arrays, Kernels* out) {
   case 3: return find_part<SET, ST, 3>(order, arrays, out);
   case 4: return find_part<SET, ST, 4>(order, arrays, out);
   case 5: return find_part<SET, ST, 5>(order, arrays, out);
+  case GLC_P4: return find_part<SET, ST, GLC_P4>(order, arrays, out);
   default: return false;
   }
 }

@@ -29,6 +29,16 @@ inline int moment_blocks(int64_t ncell) {
   return int(b < MOMENT_BLOCKS ? (b < 1 ? 1 : b) : MOMENT_BLOCKS);
 }
 
+// The paper's cell-wise support (p = 4, the order of all its runs) is built for
+// the weakly compressible sets of its Taylor-Green study and D2Q9, in FP64
+// and FP32, forward step only.
+constexpr int GLC_P4 = GLC_BASE + 4;
+template <int SET, int ST>
+constexpr bool glc_built() {
+  return (SET == D2Q9 || SET == D3Q13 || SET == D3Q21 || SET == D3Q27 || SET == D3V27) &&
+         (ST == ST_F64 || ST == ST_F32);
+}
+
 // Which combinations are compiled.  Every set gets the forward step for each
 // stencil length 2..5 (1: the on-lattice copy, D2Q9 and D3Q27 only).
 // Hermite orders: N = 2 everywhere; N = 3 for the degree-7 set (D3V27); N = 4
@@ -41,6 +51,7 @@ constexpr bool combo_built() {
   constexpr int D = Set<SET>::D;
   constexpr int deg = Set<SET>::degree;
   if (2 * N > deg) return false;
+  if constexpr (Support<NS>::glc) return glc_built<SET, ST>() && A == 1 && N == (deg == 7 ? 3 : 2);
   if (N == 3 && deg != 7) return false;
   if (A == 2 && N != 4) return false;
   if (NS == 1 && !(SET == D2Q9 || SET == D3Q27)) return false;
@@ -56,12 +67,14 @@ template <int SET, int NS, int N, int A, int ST, int MODE>
 constexpr bool mode_built() {
   if (!combo_built<SET, NS, N, A, ST>()) return false;
   if (MODE == MODE_STEP) return true;
+  if (Support<NS>::glc) return false;
   return A == 1 && N == 2 && (ST == ST_F64 || ST == ST_F32);
 }
 
 // Which (set, storage, stencil length) parts exist as compiled units.
 template <int SET, int ST, int NS>
 constexpr bool part_exists() {
+  if (Support<NS>::glc) return glc_built<SET, ST>();
   if (NS == 1 && !(SET == D2Q9 || SET == D3Q27)) return false;
   if ((ST == ST_BF16 || ST == ST_F16) && Set<SET>::D != 3) return false;
   return true;

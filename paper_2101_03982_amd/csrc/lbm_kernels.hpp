@@ -184,12 +184,37 @@ enum Mode : int {
   MODE_ADJ_STREAM = 3   // lam = S^T nu
 };
 
+// Streaming supports.  NS <= GLC_BASE: a uniform grid with an NS-node Lagrange
+// stencil around the departure point, the same for every node.
+// NS = GLC_BASE + p: the paper's cell-wise interpolation (Sec. 3, eq.
+// sl_streaming): every axis is cut into cells of p + 1 Gauss-Lobatto-Chebyshev
+// support points (neighbouring cells share their end points), and a node's
+// departure point is interpolated with the points of the cell that holds it.
+// The weights then depend on the node's phase k (its index within its cell,
+// 0..p-1) as well as on the population.  Over the p phases the source cells
+// are two neighbours at most, so one window of 2p + 1 nodes, starting dmin p
+// nodes from the arrival node's cell (dmin the lower source cell's offset),
+// serves every phase: the tables hold the window's weights per (population,
+// axis, phase), zero outside the phase's own source cell, and a compact form
+// (the phase's first window node and its p + 1 weights).
+constexpr int GLC_BASE = 16;
+template <int NS>
+struct Support {
+  static constexpr bool glc = NS > GLC_BASE;
+  static constexpr int p = glc ? NS - GLC_BASE : 1;  // cell order: phases per axis
+  static constexpr int win = glc ? 2 * p + 1 : NS;   // window nodes of one output
+  static constexpr int halo = glc ? p + 1 : NS - 1;  // source nodes beyond a tile of whole cells
+  static constexpr int xent = 8;                     // compact entry: first node, p + 1 weights, padding
+};
+
 struct KParams {
   const void* src;     // populations interpolated with the forward stencil (f)
   const void* src2;    // second input: lam (ADJ_COLLIDE) or nu (ADJ_STEP / ADJ_STREAM)
   void* dst;
   const int* off;      // [Q][3] first-node offsets, forward stencil
-  const void* wts;     // [Q][3][NS] weights (compute type), forward stencil
+  const void* wts;     // [Q][3][NS] weights (compute type), forward stencil;
+                       // cell-wise support: [Q][3][p][2p + 1] window weights per phase
+  const void* glcx;    // cell-wise support: [Q][3][p][8] compact entries (compute type)
   const int* off_t;    // transposed stencil (adjoint modes)
   const void* wts_t;
   int n[3];            // nx, ny, nz
@@ -198,6 +223,8 @@ struct KParams {
   int tiles[3];        // tiles along x, y (3D) / outer (2D), z (3D)
   int chunk;           // tiles per XCD
   int rsy, rsz;        // 3D: y and z tiles of each XCD's block of the grid (0: linear order)
+  int by, bz;          // 3D brick order: bricks of by x bz (y, z) tiles (0: x, y, z order)
+  int cus;             // compute units of the device (host input: sizes the brick order)
   double omega;        // 1 / tau (weakly compressible)
   double tau_m_half;   // tau_ref - 1/2 (compressible)
   double cv2mD;        // 2 C_v - D
@@ -260,11 +287,13 @@ struct Tile {
   // such blocks still fit on a compute unit and measured faster: the 17-21
   // velocity sets (3 %) and the FP32 f + g kernels with one cell per thread
   // (5-7 %); four elsewhere
+  // (cell-wise support: four, a whole number of cells)
   static constexpr int NW =
-      ((D == 3 && A == 1 && RO == 4 && S::Q > 16 && S::Q <= 21) || (D == 3 && A == 2 && RO == 1 && ST == ST_F32))
+      (!Support<NS>::glc && ((D == 3 && A == 1 && RO == 4 && S::Q > 16 && S::Q <= 21) ||
+                             (D == 3 && A == 2 && RO == 1 && ST == ST_F32)))
           ? 8 : 4;
   static constexpr int NT = 64 * NW;                 // threads per block
-  static constexpr int H = NS - 1;
+  static constexpr int H = Support<NS>::halo;
   static constexpr int PX = TX + ((H + 2) & ~1);     // widest LDS row (even: pairs of x)
   static constexpr int PM = (D == 3) ? NW + H : NW;  // rows per outer plane in P
   static constexpr int TOUT = (D == 3) ? RO : NW * RO;  // outer extent of the tile
@@ -274,6 +303,8 @@ struct Tile {
 
 // Per-thread / per-block geometry
 struct Geo {
+  const void* glcx;      // cell-wise support: compact table [Q][3][p][8] (global)
+  const void* xlds;      // cell-wise support: the x entries [Q][p][8], staged in LDS
   int x0, m0, o0;        // tile origin: inner (x), middle (y, 3D), outer (z or y)
   int nx, nm, no;        // extents along inner, middle, outer
   int bcx, bcm, bco;
@@ -328,8 +359,22 @@ struct PopShape {
   static constexpr bool mm = NS > 1 && D == 3 && S::moves(q, 1);
   static constexpr bool mo = NS > 1 && S::moves(q, D - 1);
   static constexpr bool direct = !mx && !mm;  // no LDS: each thread loads its own column
-  static constexpr int HX = mx ? NS - 1 : 0, HM = mm ? NS - 1 : 0, HO = mo ? NS - 1 : 0;
-  static constexpr int KX = mx ? NS : 1, KM = mm ? NS : 1, KO = mo ? NS : 1;
+  using SP = Support<NS>;
+  // cell-wise support: along x and y the tile is a whole number of cells and
+  // needs p + 1 more source nodes; along the outer axis a thread's RO rows lie
+  // in one cell (RO divides p), whose window of 2p + 1 rows it loads
+  static constexpr int HX = mx ? SP::halo : 0, HM = mm ? SP::halo : 0;
+  static constexpr int HO = mo ? (SP::glc ? SP::win - RO : NS - 1) : 0;
+  // taps: uniform NS per axis; cell-wise: the phase's own p + 1 along x and
+  // y (from a per-phase first node), the padded window along the outer axis
+  static constexpr int KX = mx ? (SP::glc ? SP::p + 1 : NS) : 1;
+  static constexpr int KM = mm ? (SP::glc ? SP::p + 1 : NS) : 1;
+  static constexpr int KO = mo ? SP::win : 1;
+  static_assert(!SP::glc || (SP::p % RO == 0 && (D == 2 || TL::NW % SP::p == 0) && TL::TX % SP::p == 0),
+                "cell-wise tiles must consist of whole cells");
+  // 2D: a thread's outer rows are one cell, so that every load column's rows
+  // have the phases 0..p-1 of the weights the thread holds
+  static_assert(!SP::glc || D == 3 || RO == SP::p, "2D cell-wise tiles: one cell per thread");
   // 3D populations through LDS load x in pairs of adjacent nodes (one
   // two-element load per pair; the window starts at an even node, so it may
   // begin one node early: sh below)
@@ -386,6 +431,16 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
   const E* base[A];
 #pragma unroll
   for (int a = 0; a < A; ++a) base[a] = src + int64_t(a * Q + q) * pstride;
+
+  // element offset of load row r of a thread whose first cell row is ob (vob
+  // valid rows): rows ob + oo .. (uniform stencil, dead rows repeat the last
+  // valid one), or the window of the cell holding ob (cell-wise support)
+  auto row_at = [&](int ob, int vob, int r) -> int {
+    if constexpr (PS::SP::glc && PS::mo)
+      return wrap_idx(ob - ob % PS::SP::p + oo + r, g.no, g.bco) * g.so;
+    else
+      return wrap_idx(ob + oo + min(r, vob - 1 + HO), g.no, g.bco) * g.so;
+  };
 
   int col[PS::ROUNDS], ob[PS::ROUNDS], vo[PS::ROUNDS];
   int col2[PS::ROUNDS];   // X2: column of the pair's second node
@@ -459,7 +514,7 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
         if (pair[rr]) {
 #pragma unroll
           for (int r = 0; r < RO + HO; ++r) {
-            const int row = wrap_idx(g.o0 + oo + min(r, g.vo - 1 + HO), g.no, g.bco) * g.so;
+            const int row = row_at(g.o0, g.vo, r);
 #pragma unroll
             for (int a = 0; a < A; ++a)
               TR::ldb2(rs[a], boff<E>(col[rr]), boff<E>(row), in.v[rr][a][r][0], in.v[rr][a][r][1]);
@@ -467,7 +522,7 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
         } else {
 #pragma unroll
           for (int r = 0; r < RO + HO; ++r) {
-            const int row = wrap_idx(g.o0 + oo + min(r, g.vo - 1 + HO), g.no, g.bco) * g.so;
+            const int row = row_at(g.o0, g.vo, r);
 #pragma unroll
             for (int a = 0; a < A; ++a) {
               in.v[rr][a][r][0] = TR::ldb(rs[a], boff<E>(col[rr]), boff<E>(row));
@@ -483,7 +538,7 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
       if (PS::direct || PS::NCOL % TL::NT == 0 || rr + 1 < PS::ROUNDS || g.tid + TL::NT * rr < PS::NCOL) {
 #pragma unroll
         for (int r = 0; r < RO + HO; ++r) {
-          const int row = wrap_idx(ob[rr] + oo + min(r, vo[rr] - 1 + HO), g.no, g.bco) * g.so;
+          const int row = row_at(ob[rr], vo[rr], r);
 #pragma unroll
           for (int a = 0; a < A; ++a) {
             if constexpr (D == 3)
@@ -510,21 +565,66 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
 // Stencil weights of population q along x, y and the outer axis (scalar
 // loads, read when the population is interpolated rather than with its HBM
 // loads, so that they do not hold scalar registers while the loads are in
-// flight).
+// flight).  Uniform support: one set per axis (wm[0], wo[0]).  Cell-wise
+// support: along x the lane's own phase (first window node bx and p + 1
+// weights, from the LDS copy of the compact table); along y one compact
+// entry per phase of the tile's rows (bm, wm); along the outer axis the
+// padded window weights of each of the thread's RO rows (wo[r]).
 template <int SET, int NS, int A, int ST, int RO, int q>
 struct PopW {
   using PS = PopShape<SET, NS, A, ST, RO, q>;
   using R = typename StoreT<ST>::real;
-  R wx[PS::KX], wm[PS::KM], wo[PS::KO];
-  __device__ __forceinline__ explicit PopW(const R* __restrict__ wts) {
+  static constexpr bool G = PS::SP::glc;
+  static constexpr int P = PS::SP::p;
+  R wx[PS::KX], wm[G ? P : 1][PS::KM], wo[G ? RO : 1][PS::KO];
+  int bx, bm[G ? P : 1];
+  __device__ __forceinline__ PopW(const R* __restrict__ wts, const Geo& g) {
     constexpr int axm = 1, axo = PS::D - 1;
     const cptr<R> wc = as_const(wts);
+    bx = 0;
+    bm[0] = 0;
+    if constexpr (!G) {
 #pragma unroll
-    for (int k = 0; k < PS::KX; ++k) wx[k] = PS::mx ? wc[(3 * q + 0) * NS + k] : R(1);
+      for (int k = 0; k < PS::KX; ++k) wx[k] = PS::mx ? wc[(3 * q + 0) * NS + k] : R(1);
 #pragma unroll
-    for (int k = 0; k < PS::KM; ++k) wm[k] = PS::mm ? wc[(3 * q + axm) * NS + k] : R(1);
+      for (int k = 0; k < PS::KM; ++k) wm[0][k] = PS::mm ? wc[(3 * q + axm) * NS + k] : R(1);
 #pragma unroll
-    for (int k = 0; k < PS::KO; ++k) wo[k] = PS::mo ? wc[(3 * q + axo) * NS + k] : R(1);
+      for (int k = 0; k < PS::KO; ++k) wo[0][k] = PS::mo ? wc[(3 * q + axo) * NS + k] : R(1);
+    } else {
+      constexpr int XE = PS::SP::xent, W = PS::SP::win;
+      if constexpr (PS::mx) {
+        const R* e = static_cast<const R*>(g.xlds) + (q * P + g.lane % P) * XE;
+        bx = int(e[0]);
+#pragma unroll
+        for (int t = 0; t < PS::KX; ++t) wx[t] = e[1 + t];
+      } else {
+        wx[0] = R(1);
+      }
+      if constexpr (PS::mm) {
+        const cptr<R> gc = as_const(static_cast<const R*>(g.glcx));
+#pragma unroll
+        for (int k = 0; k < P; ++k) {
+          bm[k] = int(gc[((3 * q + axm) * P + k) * XE]);
+#pragma unroll
+          for (int t = 0; t < PS::KM; ++t) wm[k][t] = gc[((3 * q + axm) * P + k) * XE + 1 + t];
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < P; ++k) wm[k][0] = R(1);
+      }
+      // phase of the thread's first outer row; its RO rows lie in one cell
+      const int ob = (PS::D == 3) ? g.o0 : g.o0 + g.w * RO;
+      const int k0 = ob % P;
+#pragma unroll
+      for (int r = 0; r < RO; ++r) {
+        if constexpr (PS::mo) {
+#pragma unroll
+          for (int u = 0; u < W; ++u) wo[r][u] = wc[((3 * q + axo) * P + k0 + r) * W + u];
+        } else {
+          wo[r][0] = R(1);
+        }
+      }
+    }
   }
 };
 
@@ -552,10 +652,16 @@ __device__ __forceinline__ void stage_A(const Geo& g, PopIn<SET, NS, A, ST, RO, 
       for (int r = 0; r < RO; ++r) {
         if constexpr (KO == 1) {
           res[a][r] = v[a][r][k];
-        } else {
-          R s = v[a][r][k] * w.wo[0];
+        } else if constexpr (PS::SP::glc) {
+          // the padded window of the row's cell, weights of the row's phase
+          R s = v[a][0][k] * w.wo[r][0];
 #pragma unroll
-          for (int t = 1; t < KO; ++t) s = fma(w.wo[t], v[a][r + t][k], s);
+          for (int u = 1; u < KO; ++u) s = fma(w.wo[r][u], v[a][u][k], s);
+          res[a][r] = s;
+        } else {
+          R s = v[a][r][k] * w.wo[0][0];
+#pragma unroll
+          for (int t = 1; t < KO; ++t) s = fma(w.wo[0][t], v[a][r + t][k], s);
           res[a][r] = s;
         }
       }
@@ -596,15 +702,28 @@ __device__ __forceinline__ void stage_B(const Geo& g, const PopW<SET, NS, A, ST,
       const int c = c0 + g.tid;
       if (NB % TL::NT == 0 || c < NB) {
         const int xs = c % PS::CXL, ar = c / PS::CXL;
-        R colv[TL::NW + HM];
+        if constexpr (PS::SP::glc) {
+          // row m (phase m % p): p + 1 rows from its cell's first window row
+          constexpr int PP = PS::SP::p;
 #pragma unroll
-        for (int m = 0; m < TL::NW + HM; ++m) colv[m] = P[(ar * PM + m) * PX + xs + sh];
+          for (int m = 0; m < TL::NW; ++m) {
+            const R* col = P + (ar * PM + (m - m % PP) + w.bm[m % PP]) * PX + xs + sh;
+            R s = col[0] * w.wm[m % PP][0];
 #pragma unroll
-        for (int m = 0; m < TL::NW; ++m) {
-          R s = colv[m] * w.wm[0];
+            for (int k = 1; k < KM; ++k) s = fma(w.wm[m % PP][k], col[k * PX], s);
+            T[(ar * TL::NW + m) * PX + xs] = s;
+          }
+        } else {
+          R colv[TL::NW + HM];
 #pragma unroll
-          for (int k = 1; k < KM; ++k) s = fma(w.wm[k], colv[m + k], s);
-          T[(ar * TL::NW + m) * PX + xs] = s;
+          for (int m = 0; m < TL::NW + HM; ++m) colv[m] = P[(ar * PM + m) * PX + xs + sh];
+#pragma unroll
+          for (int m = 0; m < TL::NW; ++m) {
+            R s = colv[m] * w.wm[0][0];
+#pragma unroll
+            for (int k = 1; k < KM; ++k) s = fma(w.wm[0][k], colv[m + k], s);
+            T[(ar * TL::NW + m) * PX + xs] = s;
+          }
         }
       }
     }
@@ -628,7 +747,9 @@ __device__ __forceinline__ void stage_C(const Geo& g, const PopW<SET, NS, A, ST,
     for (int a = 0; a < A; ++a)
 #pragma unroll
       for (int r = 0; r < RO; ++r) {
-        const R* row = X + ((a * RO + r) * XR + g.w) * PX + g.lane + (PS::mm ? 0 : sh);
+        // cell-wise support: the lane's cell's first window node, plus its phase's offset
+        const int lx = PS::SP::glc && PS::mx ? g.lane - g.lane % PS::SP::p + w.bx : g.lane;
+        const R* row = X + ((a * RO + r) * XR + g.w) * PX + lx + (PS::mm ? 0 : sh);
         if constexpr (KX == 1) {
           out[a][r] = row[0];
         } else {
@@ -659,7 +780,7 @@ __device__ __forceinline__ void pop_finish(const Geo& g, PopIn<SET, NS, A, ST, R
                                            typename StoreT<ST>::real* P, typename StoreT<ST>::real* T,
                                            typename StoreT<ST>::real (&out)[A][RO]) {
   using PS = PopShape<SET, NS, A, ST, RO, q>;
-  const PopW<SET, NS, A, ST, RO, q> w(wts);
+  const PopW<SET, NS, A, ST, RO, q> w(wts, g);
   stage_A(g, in, w, P, out);
   if constexpr (!PS::direct) {
     __syncthreads();
@@ -684,8 +805,8 @@ __device__ __forceinline__ void pair_finish(const Geo& g, PopIn<SET, NS, A, ST, 
                                             typename StoreT<ST>::real (&out1)[A][RO]) {
   using PS0 = PopShape<SET, NS, A, ST, RO, q0>;
   using PS1 = PopShape<SET, NS, A, ST, RO, q1>;
-  const PopW<SET, NS, A, ST, RO, q0> w0(wts);
-  const PopW<SET, NS, A, ST, RO, q1> w1(wts);
+  const PopW<SET, NS, A, ST, RO, q0> w0(wts, g);
+  const PopW<SET, NS, A, ST, RO, q1> w1(wts, g);
   stage_A(g, in0, w0, P0, out0);
   stage_A(g, in1, w1, P1, out1);
   if constexpr (!PS0::direct || !PS1::direct) {
@@ -821,10 +942,11 @@ struct Pipe {
   }
 };
 
-// Populations grouped per pair of barriers in the forward pass.
-template <int D, int A, int ST, int MODE>
+// Populations grouped per pair of barriers in the forward pass (one at a
+// time for the cell-wise support, whose wider windows hold more registers).
+template <int D, int NS, int A, int ST, int MODE>
 constexpr int pipe_group() {
-  return (D == 3 && A == 1 && MODE == MODE_STEP) ? 2 : 1;
+  return (D == 3 && A == 1 && MODE == MODE_STEP && !Support<NS>::glc) ? 2 : 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -940,11 +1062,17 @@ void sl_kernel(KParams p) {
   constexpr int RO = cells_per_thread<D, Q, A, ST, MODE>();
   using TL = Tile<SET, NS, A, ST, RO>;
 
-  constexpr int GROUP = pipe_group<D, A, ST, MODE>();
+  constexpr int GROUP = pipe_group<D, NS, A, ST, MODE>();
   __shared__ __align__(16) R P_lds[2 * GROUP][TL::PSZ];
   __shared__ __align__(16) R T_lds[2][TL::TSZ];
+  // cell-wise support: the compact x entries of every population and phase
+  using SP = Support<NS>;
+  constexpr int XT = SP::glc ? Q * SP::p * SP::xent : 1;
+  __shared__ __align__(16) R X_lds[XT];
 
   Geo g;
+  g.glcx = p.glcx;
+  g.xlds = X_lds;
   g.tid = threadIdx.x;
   g.lane = threadIdx.x & 63;
   g.w = threadIdx.x >> 6;
@@ -952,15 +1080,34 @@ void sl_kernel(KParams p) {
   g.bcx = p.bc[0];
   // XCD-aware tile order: hardware blocks go round-robin to the 8 XCDs.  Each
   // XCD gets one block of the grid (3D: a 2 x 4 split of the y and z tiles,
-  // so that the halo planes two XCDs both read are few), walked x, y, z, so
-  // that the halo rows shared by neighbouring tiles are read through its L2.
+  // so that the halo planes two XCDs both read are few).  The XCD walks it so
+  // that the tiles it holds at once, which read each other's halo rows, are
+  // neighbours: x, y, z when its xy plane of tiles is small against the
+  // blocks it runs at once (the z neighbours then run together too); else in
+  // bricks of by x bz (y, z) tiles, z fastest, the bricks walked x, y, z, so
+  // that tiles one or two cells thick along z do not wait a whole plane of
+  // tiles for the neighbours that re-read three of their four source planes
+  // (which L2 and the Infinity Cache no longer hold by then).
   const int bid = blockIdx.x;
   const int xcd = bid & 7, lt = bid >> 3;
   int tix, tiy, tiz;
   if (p.rsy > 0) {
-    tix = lt % p.tiles[0];
-    const int rest = lt / p.tiles[0];
-    const int ly = rest % p.rsy, lz = rest / p.rsy;
+    int ly, lz;
+    if (p.bz > 0) {
+      const int nby = (p.rsy + p.by - 1) / p.by;
+      const int per = p.by * p.bz;
+      const int brick = lt / per, w = lt % per;
+      tix = brick % p.tiles[0];
+      const int bb = brick / p.tiles[0];
+      ly = (bb % nby) * p.by + w / p.bz;
+      lz = (bb / nby) * p.bz + w % p.bz;
+      if (ly >= p.rsy) return;
+    } else {
+      tix = lt % p.tiles[0];
+      const int rest = lt / p.tiles[0];
+      ly = rest % p.rsy;
+      lz = rest / p.rsy;
+    }
     tiy = (xcd & 1) * p.rsy + ly;
     tiz = (xcd >> 1) * p.rsz + lz;
     if (lz >= p.rsz || tiy >= p.tiles[1] || tiz >= p.tiles[2]) return;
@@ -989,6 +1136,14 @@ void sl_kernel(KParams p) {
     g.o0 = tiy * TL::TOUT;
     g.vm = 1;
     g.vo = min(TL::TOUT, g.no - g.o0);
+  }
+
+  if constexpr (SP::glc) {
+    // stage the x entries ([Q][p][8] of the [Q][3][p][8] table) in LDS
+    const R* __restrict__ gx = static_cast<const R*>(p.glcx);
+    constexpr int PE = SP::p * SP::xent;
+    for (int i = g.tid; i < XT; i += TL::NT) X_lds[i] = gx[(3 * (i / PE)) * PE + i % PE];
+    __syncthreads();
   }
 
   const E* __restrict__ src = static_cast<const E*>(p.src);

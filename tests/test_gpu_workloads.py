@@ -6,8 +6,10 @@ closed forms.
 * 2D Taylor-Green vortex, D2Q9, 64^2, FP64, 1000 steps: the whole state within
   1e-12 of the oracle, kinetic energy log within 1e-12, viscous decay.
 * 3D Taylor-Green vortex at the full 128^3, FP32, four sets: one step at
-  sampled cells against the oracle; mass and momentum conservation and
-  monotone kinetic-energy decay over 100 steps.
+  sampled cells against the oracle (per population, 1e-5 of each
+  population's own scale; the Ma 0.1 deviations from w_i are small);
+  mass and momentum conservation and monotone
+  kinetic-energy decay over 100 steps.
 * Kinetic energy of FP32 runs within 1e-5 of the FP64 oracle (24^3, 100 steps).
 """
 import math
@@ -17,7 +19,7 @@ import pytest
 import torch
 
 import lbm_inputs as W
-from gpu_helpers import gpu_populations, init_both, pair, rel_err, to_dev
+from gpu_helpers import gpu_populations, init_both, note, pair, rel_err, to_dev
 from paper_2101_03982_amd import Lattice
 
 pytestmark = pytest.mark.gpu
@@ -65,20 +67,26 @@ def test_tgv2d_full_run_matches_oracle(orc):
 
 @pytest.mark.parametrize("name", W.TGV3D_SETS)
 def test_tgv3d_full_size_sampled(orc, name):
-    """128^3 FP32, one step, 96 sampled cells against the oracle computed one by one."""
+    """128^3 FP32, one step, 96 sampled cells against the oracle computed one
+    by one, from the same float-rounded initial fields."""
     wl = W.tgv3d_workload(name, n=128)
     lat = Lattice(name, wl.grid, wl.tau, wl.order, stencil=wl.stencil, storage="f32", dx=wl.dx, dt=wl.dt,
                   cs=wl.cs, device="cuda:0")
     cfg = orc.Config(name, wl.grid, tau=wl.tau, order=wl.order, stencil=wl.stencil, dx=wl.dx, dt=wl.dt, cs=wl.cs)
     rho, u, _ = W.tgv3d_fields(wl)
+    # both sides start from the same float-rounded fields (rho - 1 ~ 1e-3)
+    rho, u = rho.astype(np.float32).astype(np.float64), u.astype(np.float32).astype(np.float64)
     lat.init_equilibrium(to_dev(rho, torch.float32), to_dev(u, torch.float32))
     lat.step(1)
     cells = np.random.default_rng(11).choice(wl.ncell, size=96, replace=False)
     cells[:4] = [0, wl.ncell - 1, 127, 128 * 128 * 64 + 63]  # corners and tile edges
     ref = orc.first_step_at(cfg, rho, u, cells)
-    w = torch.tensor(lat.table()["w"], dtype=torch.float64, device="cuda:0").reshape(-1, 1)
-    got = (lat.state().reshape(lat.Q, -1)[:, torch.from_numpy(cells).cuda()].double() + w).cpu().numpy().T
-    assert rel_err(got, ref) <= 3e-6
+    w = np.array(lat.table()["w"])
+    got = lat.state().reshape(lat.Q, -1)[:, torch.from_numpy(cells).cuda()].double().cpu().numpy().T + w
+    # per population, against its own largest deviation from w_i
+    err = float(np.max(np.max(np.abs(got - ref), axis=0) / np.max(np.abs(ref - w), axis=0)))
+    note("tgv3d_full_sampled_%s" % name, err=err)
+    assert err <= 1e-5, err  # measured 1.7e-6 (D3Q21) to 3.3e-6 (D3V27, N = 3)
 
 
 @pytest.mark.parametrize("name", W.TGV3D_SETS)

@@ -132,6 +132,12 @@ def _create(L, set_id, grid, tau=0.8, order=2, **opt):
     ((5, (2048, 2048, 1024), 0.8, 2), -1),                   # 2^32 cells
     ((7, (8, 8, 8), 0.8, 4, {"compressible": 1, "energy_f64": 1}), -4),  # FP64 energy sum: 16-bit only
     ((5, (8, 8, 8), 0.8, 2, {"storage": 2, "energy_f64": 1}), -4),       # ... and compressible only
+    ((5, (8, 8, 8), 0.8, 2, {"support": 1, "stencil": 4}), -4),          # cell-wise support: p = 4 only
+    ((5, (10, 8, 8), 0.8, 2, {"support": 1, "stencil": 5}), -1),         # extents: whole cells
+    ((5, (8, 8, 8), 0.8, 2, {"support": 1, "stencil": 5, "boundary": (1, 0, 0)}), -4),  # periodic only
+    ((7, (8, 8, 8), 0.8, 4, {"support": 1, "stencil": 5, "compressible": 1}), -4),      # not built
+    ((5, (8, 8, 8), 0.8, 2, {"support": 1, "stencil": 5, "storage": 2}), -4),           # FP64 / FP32 only
+    ((5, (8, 8, 8), 0.8, 2, {"support": 2}), -1),                                       # unknown support
 ])
 def test_create_rejects(L, args, code):
     set_id, grid = args[0], args[1]
