@@ -209,6 +209,20 @@ int lbm_step_into(lbm_ctx *ctx, const void *src, void *dst);
  * rho <= 0 or theta <= 0. */
 int lbm_moments(lbm_ctx *ctx, const void *state, void *rho, void *u, void *theta, lbm_diag *diag);
 
+/* lbm_moments for callers that cannot allocate memory (HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same kernels,
+ * results and errors, but the block sums go to a static device array of the
+ * library (1025 x 9 doubles, 73.8 KB per device, held until the process
+ * ends) instead of the context's scratch, and the nine global sums come back
+ * through a buffer on the caller's stack; the call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine).  Every call on one
+ * device shares that array: calls that overlap on one device (several
+ * streams or threads) race and must be serialized by the caller.  Nothing in
+ * the array needs to start at zero: each call writes every element it reads.
+ * LBM_EINVAL if the reduction would need more than the array holds (it
+ * cannot with the current block count; checked). */
+int lbm_moments_noalloc(lbm_ctx *ctx, const void *state, void *rho, void *u, void *theta, lbm_diag *diag);
+
 /* Enstrophy E = <|curl u|^2> of a velocity field (Sec. 4.2: the squared
  * vorticity integrated over the domain and divided by its volume; on the
  * uniform periodic grid, the mean over the nodes), written to *enstrophy

@@ -73,6 +73,7 @@ _SIGS = {
     "lbm_step": (ctypes.c_int, [_V, _I64]),
     "lbm_step_into": (ctypes.c_int, [_V, _P, _P]),
     "lbm_moments": (ctypes.c_int, [_V, _P, _P, _P, _P, ctypes.POINTER(Diag)]),
+    "lbm_moments_noalloc": (ctypes.c_int, [_V, _P, _P, _P, _P, ctypes.POINTER(Diag)]),
     "lbm_enstrophy": (ctypes.c_int, [_V, _P, _I32, ctypes.POINTER(_D)]),
     "lbm_sync": (ctypes.c_int, [_V]),
     "lbm_set_stream": (ctypes.c_int, [_V, _P]),

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -85,6 +86,89 @@ void quantize_unit_sum(double* L, int n, int bits) {
 
 }  // namespace
 
+// Reduction scratch of lbm_moments_noalloc: a file-scope device array, so
+// that the call allocates nothing.  Each device holds its own copy; its
+// address on a device comes from hipGetSymbolAddress (the array's name in
+// host code is not a device address).  Calls that overlap on one device
+// share it and race.
+constexpr size_t SCRATCH_DOUBLES = size_t(MOMENT_BLOCKS + 1) * NPART;
+static __device__ __align__(256) double scratch[SCRATCH_DOUBLES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of `scratch` on `device`, looked up once per device with
+// that device current (the caller has made it current).
+int scratch_address(int device, void** out) {
+  if (device < 0 || device >= MAX_DEVICES) return fail(LBM_EINVAL, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[device]) {
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[device] = ptr;
+  }
+  *out = g_scratch_ptr[device];
+  return LBM_OK;
+}
+
+// Cell-wise streaming on Gauss-Lobatto-Chebyshev support points (Sec. 3, eq.
+// sl_streaming) along one axis, for a population moving s mean node spacings
+// per step: cells of p intervals; node k of a cell (k < p) departs from
+// r = xg_k - s / p cells past its cell's start, xg_k = (1 - cos(pi k / p)) / 2,
+// which lies in the cell floor(r) cells on, at eta = r - floor(r); its value
+// is sum_t psi_t(eta) f(node t of that cell), psi_t the Lagrange polynomials
+// through the cell's p + 1 points.  Out: the window offset dmin p (dmin the
+// lowest floor(r) over the phases); per phase k, the window weights
+// W[k][0..2p] (the phase's p + 1 weights from node b_k = (floor(r_k) -
+// dmin) p, zero elsewhere) and the compact entry X[k] = {b_k, psi_0..psi_p,
+// 0, 0}.  The weights of each phase are quantized to sum to one (bits as in
+// quantize_unit_sum).  Returns false if the phases span more than two cells.
+bool glc_axis(double s, int p, int bits, int* off, double* W, double* X) {
+  const double pi = 3.14159265358979323846;
+  auto xg = [&](int m) { return 0.5 * (1.0 - std::cos(pi * double(m) / double(p))); };
+  int d[8];
+  double psi[8][8];
+  int dmin = 1 << 30, dmax = -(1 << 30);
+  for (int k = 0; k < p; ++k) {
+    const double r = xg(k) - s / double(p);
+    const double fl = std::floor(r);
+    const double eta = r - fl;
+    d[k] = int(fl);
+    dmin = std::min(dmin, d[k]);
+    dmax = std::max(dmax, d[k]);
+    for (int t = 0; t <= p; ++t) {
+      double num = 1.0, den = 1.0;
+      for (int m = 0; m <= p; ++m) {
+        if (m == t) continue;
+        num *= eta - xg(m);
+        den *= xg(t) - xg(m);
+      }
+      psi[k][t] = num / den;
+    }
+    quantize_unit_sum(psi[k], p + 1, bits);
+  }
+  if (dmax > dmin + 1) return false;
+  *off = dmin * p;
+  const int win = 2 * p + 1;
+  for (int k = 0; k < p; ++k) {
+    const int b = (d[k] - dmin) * p;
+    for (int u = 0; u < win; ++u) W[k * win + u] = 0.0;
+    for (int u = 0; u < 8; ++u) X[k * 8 + u] = 0.0;
+    X[k * 8] = double(b);
+    for (int t = 0; t <= p; ++t) {
+      W[k * win + b + t] = psi[k][t];
+      X[k * 8 + 1 + t] = psi[k][t];
+    }
+  }
+  return true;
+}
+
+}  // namespace
+
 struct lbm_ctx {
   int set = 0, D = 0, Q = 0, A = 1, order = 2, ns_user = 4, ns = 4, storage = LBM_F32;
   int degree = 0;
@@ -109,6 +193,7 @@ struct lbm_ctx {
   double* d_partial = nullptr;
   double* d_result = nullptr;
   double* h_result = nullptr;
+  void* scratch = nullptr;  // device address of the static scratch on `device`
   bool onlattice = false;
   double sw = 0, swx[3] = {0, 0, 0}, swX = 0;
 };
@@ -631,6 +716,13 @@ int lbm_create(lbm_ctx** out, int32_t set, const int64_t grid[3], double tau, in
     delete c;
     return fail(rc, m);
   }
+  rc = scratch_address(c->device, &c->scratch);
+  if (rc != LBM_OK) {
+    std::string m = g_last_error;
+    release(c);
+    delete c;
+    return fail(rc, m);
+  }
   if (hipMalloc(&c->d_partial, sizeof(double) * MOMENT_BLOCKS * NPART) != hipSuccess ||
       hipMalloc(&c->d_result, sizeof(double) * NPART) != hipSuccess ||
       hipHostMalloc(&c->h_result, sizeof(double) * NPART, hipHostMallocDefault) != hipSuccess)
@@ -822,6 +914,21 @@ int lbm_moments(lbm_ctx* c, const void* state, void* rho, void* u, void* theta, 
   if (!state) return fail(LBM_EINVAL, "no state");
   if (int r = set_device(c)) return r;
   return moments_impl(c, state, rho, u, theta, diag, c->d_partial, c->d_result, c->h_result);
+}
+
+int lbm_moments_noalloc(lbm_ctx* c, const void* state, void* rho, void* u, void* theta, lbm_diag* diag) {
+  if (int r = check_ctx(c)) return r;
+  if (!state) state = c->buf[c->cur];
+  if (!state) return fail(LBM_EINVAL, "no state");
+  const size_t need = size_t(moment_blocks(c->ncell) + 1) * NPART;
+  if (need > SCRATCH_DOUBLES)
+    return fail(LBM_EINVAL, "lbm_moments_noalloc: " + std::to_string(need) + " doubles of reduction scratch exceed " +
+                                "the static maximum of " + std::to_string(SCRATCH_DOUBLES));
+  if (int r = set_device(c)) return r;
+  double* base = static_cast<double*>(c->scratch);
+  if (!base) return fail(LBM_EINVAL, "no static scratch address for this context's device");
+  double host[NPART];
+  return moments_impl(c, state, rho, u, theta, diag, base, base + size_t(moment_blocks(c->ncell)) * NPART, host);
 }
 
 static int adjoint_ok(lbm_ctx* c) {
