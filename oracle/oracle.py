@@ -58,6 +58,7 @@ class _Cfg(ctypes.Structure):
         ("cs", ctypes.c_double),
         ("tau", ctypes.c_double),
         ("gamma", ctypes.c_double),
+        ("prandtl", ctypes.c_double),
     ]
 
 
@@ -99,6 +100,7 @@ class Config:
     gamma: float = 1.4
     bc: tuple = (PERIODIC, PERIODIC, PERIODIC)
     kind: str = "uniform"
+    prandtl: float = 1.0  # compressible model: heat fluxes relaxed for this Prandtl number
     _c: _Cfg = field(default=None, repr=False)
 
     def __post_init__(self):
@@ -114,6 +116,7 @@ class Config:
         c.kind = KINDS.index(self.kind)
         c.dx, c.dt, c.cs, c.tau, c.gamma = (float(self.dx), float(self.dt), float(self.cs),
                                             float(self.tau), float(self.gamma))
+        c.prandtl = float(self.prandtl)
         self._c = c
         self.D = table(self.set)["D"]
         self.Q = table(self.set)["Q"]

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "lbm_oracle.c")
 PINS = ["tests/test_oracle_sets.py", "tests/test_oracle_collision.py", "tests/test_oracle_stream.py",
         "tests/test_oracle_step.py", "tests/test_oracle_adjoint.py", "tests/test_oracle_moments.py",
-        "tests/test_oracle_glc.py"]
+        "tests/test_oracle_glc.py", "tests/test_oracle_prandtl.py"]
 
 MUTANTS = {
     "H2_drops_delta": ("double H2 = (xh[a] * xh[b] - kd(a, b)) / (cs * cs);",
@@ -58,6 +58,11 @@ MUTANTS = {
                        "const double r = glc_point((int)k, pp) + s / (double)pp;"),
     "glc_cell_ceil": ("const double d = floor(r);", "const double d = ceil(r);"),
     "glc_shift_in_nodes": ("- s / (double)pp;", "- s;"),
+    "qe_lattice_frame": ("      zeta[a] = p->t.xi[i][a] - u[a];", "      zeta[a] = p->t.xi[i][a];"),
+    "qe_f_basis_factor": ("(X - (D + 2.0)) / (2.0 * (D + 2.0));", "(X - (D + 2.0)) / (2.0 * (D + 4.0));"),
+    "qe_g_flux_dropped": ("qe[Q + i] = eq[Q + i] + p->t.w[i] * pg;", "qe[Q + i] = eq[Q + i];"),
+    "qe_tau_q_inverted": ("const double complex tau_q = 0.5 + (tau - 0.5) / p->c.prandtl;",
+                          "const double complex tau_q = 0.5 + (tau - 0.5) * p->c.prandtl;"),
 }
 
 
