@@ -54,7 +54,8 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates HBM byte counters)")
     ap.add_argument("--only", default=None,
-                    help="run one leg alone and print its JSON (precision, svi, svi2048, adjoint, large_grid, glc); "
+                    help="run one leg alone and print its JSON (precision, svi, svi2048, adjoint, large_grid, glc, "
+                         "prandtl); "
                          "with --precision-steps and --storages it is the profiling target of one kernel family")
     ap.add_argument("--storages", default="f64,f32,bf16,f16", help="storages of the precision leg")
     ap.add_argument("--machs", default="0.5,1.0", help="Mach numbers of the precision leg")
@@ -467,6 +468,47 @@ def glc_throughput(sets=("D3Q13", "D3Q21", "D3V27", "D3Q27"), n=128):
     return out
 
 
+def prandtl_cost(Pr=0.75):
+    """The quasi-equilibrium collision for Pr != 1 against plain BGK: single-
+    launch time of the precision workload's FP32 and FP64 kernels (D3Q45 f+g
+    256^3, Ma 1.0) and of the 2048^2 shock-vortex D2Q19 kernels, Pr = 0.75."""
+    import torch
+
+    import lbm_inputs as W
+    from paper_2101_03982_amd import Lattice
+
+    out = {}
+    wl = W.ctgv_workload(n=256, Ma=1.0)
+    rho, u, th = W.ctgv_fields(wl)
+    for st in ("f64", "f32"):
+        for pr in (1.0, Pr):
+            lat = Lattice("D3Q45", wl.grid, wl.tau, 4, stencil=wl.stencil, storage=st, dx=wl.dx, dt=wl.dt, cs=wl.cs,
+                          compressible=True, gamma=wl.gamma, prandtl=pr, device="cuda:0")
+            dt_ = lat.dtype
+            lat.init_equilibrium(torch.from_numpy(rho).to("cuda:0", dt_), torch.from_numpy(u).to("cuda:0", dt_),
+                                 torch.from_numpy(th).to("cuda:0", dt_))
+            out["D3Q45_256_%s_Pr%g_ms" % (st, pr)] = kernel_time(lat, reps=10)
+            lat.close()
+            del lat
+            torch.cuda.empty_cache()
+    sw = W.svi_workload("D2Q19", n=2048, storage="f32")
+    r2, u2, t2 = W.svi_fields(sw)
+    for st in ("f64", "f32"):
+        for pr in (1.0, Pr):
+            lat = Lattice("D2Q19", sw.grid, sw.tau, sw.order, stencil=sw.stencil, storage=st, dx=sw.dx, dt=sw.dt,
+                          cs=sw.cs, compressible=True, gamma=sw.gamma, prandtl=pr,
+                          boundary=("extrapolate", "periodic", "periodic"), device="cuda:0")
+            dt_ = lat.dtype
+            lat.init_equilibrium(torch.from_numpy(r2).to("cuda:0", dt_), torch.from_numpy(u2).to("cuda:0", dt_),
+                                 torch.from_numpy(t2).to("cuda:0", dt_))
+            out["D2Q19_2048_%s_Pr%g_ms" % (st, pr)] = kernel_time(lat)
+            lat.close()
+            del lat
+            torch.cuda.empty_cache()
+    out["workload"] = "quasi-equilibrium (Pr = %g) vs BGK: D3Q45 f+g 256^3 Ma 1.0; D2Q19 f+g 2048^2 shock-vortex" % Pr
+    return out
+
+
 def svi_throughput(n=512):
     """Shock-vortex workload (D2Q19 / D2Q25, f + g, N = 4, n = 5, extrapolating
     in x) at n^2 (512^2, the workload's size, whose two buffers fit in the
@@ -511,6 +553,7 @@ def run_only(a):
         "adjoint": adjoint_cost,
         "large_grid": large_grid,
         "glc": glc_throughput,
+        "prandtl": prandtl_cost,
     }
     if a.only not in legs:
         print("unknown leg %r (one of %s)" % (a.only, ", ".join(sorted(legs))), file=sys.stderr)
@@ -668,6 +711,7 @@ def main():
         out["svi"] = svi_throughput()
         out["svi_2048"] = svi_throughput(2048)
         out["glc"] = glc_throughput()
+        out["prandtl"] = prandtl_cost()
         out["on_lattice"] = on_lattice_ratio()
         out["dissipation"] = dissipation(sets)
         torch.cuda.empty_cache()

@@ -112,6 +112,13 @@ typedef struct lbm_options {
   double cs;             /* speed of sound the set is scaled to; <= 0: the table's own */
   double gamma;          /* heat capacity ratio (compressible; C_v = 1/(gamma - 1)) */
   void *stream;          /* hipStream_t for all work of the context; NULL = null stream */
+  double prandtl;        /* compressible model: Prandtl number (default 1: plain BGK).  Other
+                            values relax the heat fluxes of f and g, taken in the frame moving
+                            with the fluid, at 1/tau_q, tau_q = 1/2 + (tau - 1/2)/Pr, through
+                            a quasi-equilibrium (Sec. 3 names the approach; reading in the
+                            design notes), every other moment at 1/tau.  Built for D3Q45 with
+                            n = 4 and D2Q19 / D2Q25 with n = 5, LBM_F64 / LBM_F32 storage
+                            (LBM_EUNSUPPORTED otherwise). */
 } lbm_options;
 
 typedef struct lbm_diag {
@@ -128,7 +135,7 @@ typedef struct lbm_diag {
 typedef struct lbm_ctx lbm_ctx;
 
 /* Fills opt with defaults: F32 storage, n = 4, periodic, dx = dt = 1,
- * cs = table's own, gamma = 1.4, null stream. */
+ * cs = table's own, gamma = 1.4, Pr = 1, uniform support, null stream. */
 void lbm_default_options(lbm_options *opt);
 
 /* Creates a context for velocity set `set` on the grid grid[0] x grid[1] x

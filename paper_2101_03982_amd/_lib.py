@@ -32,6 +32,7 @@ class Options(ctypes.Structure):
         ("cs", ctypes.c_double),
         ("gamma", ctypes.c_double),
         ("stream", ctypes.c_void_p),
+        ("prandtl", ctypes.c_double),
     ]
 
 

@@ -190,6 +190,7 @@ struct lbm_ctx {
   void* d_glcx = nullptr;   // cell-wise support: compact per-phase entries [Q][3][p][8]
   int glc_p = 0;            // cell-wise support: cell order p (0: uniform support)
   int cus = 0;              // compute units of the device
+  double prandtl = 1.0;     // compressible model: Prandtl number (1: plain BGK)
   double* d_partial = nullptr;
   double* d_result = nullptr;
   double* h_result = nullptr;
@@ -320,6 +321,7 @@ KParams base_params(const lbm_ctx* c) {
   p.wts_t = c->d_wts_t;
   p.glcx = c->d_glcx;
   p.cus = c->cus;
+  p.inv_pr = 1.0 / c->prandtl;
   for (int a = 0; a < 3; ++a) {
     p.n[a] = int(c->n[a]);
     p.bc[a] = c->bc[a];
@@ -520,7 +522,7 @@ int launch(hipError_t e, const char* what) { return e == hipSuccess ? LBM_OK : h
 
 extern "C" {
 
-int32_t lbm_abi_version(void) { return 1; }
+int32_t lbm_abi_version(void) { return 2; }
 
 const char* lbm_strerror(int status) {
   switch (status) {
@@ -545,6 +547,7 @@ void lbm_default_options(lbm_options* opt) {
   opt->dt = 1.0;
   opt->cs = 0.0;
   opt->gamma = 1.4;
+  opt->prandtl = 1.0;
 }
 
 int lbm_set_table(int32_t set, int32_t* Q, int32_t* D, int32_t* degree, double* cs, double* w, double* xi) {
@@ -687,6 +690,11 @@ int lbm_create(lbm_ctx** out, int32_t set, const int64_t grid[3], double tau, in
   }
   if (!find_kernels(set, c->ns, order, c->A, c->storage, &c->k))
     return bad(LBM_EUNSUPPORTED, "no kernel built for this set / stencil / order / model / storage");
+  if (!(o.prandtl > 0) || !std::isfinite(o.prandtl)) return bad(LBM_EINVAL, "the Prandtl number must be positive");
+  c->prandtl = o.prandtl;
+  if (c->prandtl != 1.0 && !c->k.step_qe)
+    return bad(LBM_EUNSUPPORTED, "Pr != 1 is built for the compressible D3Q45 (n = 4) and D2Q19 / D2Q25 (n = 5) "
+                                 "models with FP64 / FP32 storage");
 
   // sums of the stored table (reference values of the deviation storage)
   for (int i = 0; i < t.Q; ++i) {
@@ -846,7 +854,9 @@ static int step_once(lbm_ctx* c, const void* src, void* dst) {
   KParams p = base_params(c);
   p.src = src;
   p.dst = dst;
-  const StepLaunch f = (c->k.step_stream && 2 * c->state_bytes > LLC_BYTES) ? c->k.step_stream : c->k.mode[MODE_STEP];
+  const bool big = 2 * c->state_bytes > LLC_BYTES;
+  StepLaunch f = (c->k.step_stream && big) ? c->k.step_stream : c->k.mode[MODE_STEP];
+  if (c->prandtl != 1.0) f = (c->k.step_qe_stream && big) ? c->k.step_qe_stream : c->k.step_qe;
   return launch(f(p, c->stream), "step kernel");
 }
 

@@ -15,6 +15,9 @@ struct Kernels {
   StepLaunch mode[4] = {nullptr, nullptr, nullptr, nullptr};  // indexed by Mode
   // the forward step with non-temporal result stores (3D sets, n = 4 only)
   StepLaunch step_stream = nullptr;
+  // the compressible forward step with the Pr != 1 quasi-equilibrium (and its
+  // streamed-store copy)
+  StepLaunch step_qe = nullptr, step_qe_stream = nullptr;
   CellLaunch init = nullptr;
   CellLaunch moments = nullptr;     // writes partials; grid = CellParams::nblocks
   CellLaunch ke_adjoint = nullptr;
@@ -68,6 +71,10 @@ constexpr bool mode_built() {
   if (!combo_built<SET, NS, N, A, ST>()) return false;
   if (MODE == MODE_STEP) return true;
   if (Support<NS>::glc) return false;
+  // the Pr != 1 quasi-equilibrium: the compressible workloads' sets and stencils, FP64 / FP32
+  if (MODE == MODE_STEP_QE)
+    return A == 2 && (ST == ST_F64 || ST == ST_F32) &&
+           ((SET == D3Q45 && NS == 4) || ((SET == D2Q19 || SET == D2Q25) && NS == 5));
   return A == 1 && N == 2 && (ST == ST_F64 || ST == ST_F32);
 }
 

@@ -109,6 +109,11 @@ bool find_kernels_part(int order, int arrays, Kernels* out) {
           out->mode[MODE_STEP] = &launch_step<SET, NS, N, A, ST, MODE_STEP>;
           if constexpr (Set<SET>::D == 3 && NS == 4)
             out->step_stream = &launch_step<SET, NS, N, A, ST, MODE_STEP, CP_STREAM>;
+          if constexpr (mode_built<SET, NS, N, A, ST, MODE_STEP_QE>()) {
+            out->step_qe = &launch_step<SET, NS, N, A, ST, MODE_STEP_QE>;
+            if constexpr (Set<SET>::D == 3 && NS == 4)
+              out->step_qe_stream = &launch_step<SET, NS, N, A, ST, MODE_STEP_QE, CP_STREAM>;
+          }
           if constexpr (mode_built<SET, NS, N, A, ST, MODE_ADJ_COLLIDE>()) {
             out->mode[MODE_ADJ_COLLIDE] = &launch_step<SET, NS, N, A, ST, MODE_ADJ_COLLIDE>;
             out->mode[MODE_ADJ_STEP] = &launch_step<SET, NS, N, A, ST, MODE_ADJ_STEP>;

@@ -181,8 +181,10 @@ enum Mode : int {
   MODE_STEP = 0,        // f' = C(S f)
   MODE_ADJ_COLLIDE = 1, // nu = J_C(S f)^T lam
   MODE_ADJ_STEP = 2,    // nu' = J_C(S f)^T (S^T nu)
-  MODE_ADJ_STREAM = 3   // lam = S^T nu
+  MODE_ADJ_STREAM = 3,  // lam = S^T nu
+  MODE_STEP_QE = 4      // f' = C(S f), compressible collision with the Pr != 1 quasi-equilibrium
 };
+constexpr bool is_step(int mode) { return mode == MODE_STEP || mode == MODE_STEP_QE; }
 
 // Streaming supports.  NS <= GLC_BASE: a uniform grid with an NS-node Lagrange
 // stencil around the departure point, the same for every node.
@@ -234,6 +236,7 @@ struct KParams {
   double swX;          // sum_i w_i |xh_i|^2
   double e64;          // nonzero: compressible energy moment summed in FP64
   double cmom1;        // 1 / sum_i w_i xh_ix^2 - 1 with the FP32-rounded constants
+  double inv_pr;       // MODE_STEP_QE: 1 / Pr
   // FP32 compressible model: defects of the FP32-rounded set's moments against
   // the Gaussian ones (MASS_* layout below), for the mass restoration
   double mdef[30];
@@ -946,7 +949,7 @@ struct Pipe {
 // time for the cell-wise support, whose wider windows hold more registers).
 template <int D, int NS, int A, int ST, int MODE>
 constexpr int pipe_group() {
-  return (D == 3 && A == 1 && MODE == MODE_STEP && !Support<NS>::glc) ? 2 : 1;
+  return (D == 3 && A == 1 && is_step(MODE) && !Support<NS>::glc) ? 2 : 1;
 }
 
 // ---------------------------------------------------------------------------
@@ -1043,7 +1046,7 @@ constexpr int sl_threads() {
 // registers cost less than the lost occupancy, measured 5-7 %), else no bound.
 template <int SET, int NS, int A, int ST, int MODE>
 constexpr int sl_min_waves() {
-  return (Set<SET>::D == 3 && A == 2 && ST == ST_F32 && MODE == MODE_STEP &&
+  return (Set<SET>::D == 3 && A == 2 && ST == ST_F32 && is_step(MODE) &&
           cells_per_thread<Set<SET>::D, Set<SET>::Q, A, ST, MODE>() == 1) ? 4 : 1;
 }
 
@@ -1224,6 +1227,9 @@ void sl_kernel(KParams p) {
   struct Mom {
     R rho, dr, ux, uy, uz, U, theta, eta, omega, Epre;
     double Epre64;
+    // MODE_STEP_QE: the co-moving non-equilibrium heat fluxes of f and g and
+    // the rate they relax at
+    R qf[3], qg[3], omq;
   };
   auto moments = [&](int r) -> Mom {
     // ---- moments (Sec. 3): rho, j~ = sum xh f (and energy sums)
@@ -1332,7 +1338,7 @@ void sl_kernel(KParams p) {
     m.Epre = Epre;
     m.Epre64 = Epre64;
     m.theta = R(1); m.eta = R(0); m.omega = R(p.omega);
-    if constexpr (MODE == MODE_STEP) {
+    if constexpr (is_step(MODE)) {
       R omega = R(p.omega), theta = R(1), eta = R(0);
       if constexpr (COMP) {
         // 2 rho C_v theta = sum |xh - u~|^2 f + sum g = E_f - rho U + G
@@ -1360,11 +1366,70 @@ void sl_kernel(KParams p) {
       }
       m.theta = theta; m.eta = eta; m.omega = omega;
     }
+    if constexpr (MODE == MODE_STEP_QE) {
+      // Quasi-equilibrium (Pr != 1): heat fluxes in the frame moving with the
+      // fluid, non-equilibrium parts, from the set's moments of the
+      // interpolated populations minus the equilibrium's closed forms
+      // (exact for sets of degree >= 7 at N = 4): contracted third moment
+      // rho u~ (U + (D + 2) theta), stress rho (u~ u~ + theta I), g flux
+      // (2 C_v - D) theta rho u~.  With deviation storage the sums run over
+      // f - w and g - (2 C_v - D) w, whose references carry I and 2 C_v - D.
+      R qa[3] = {R(0), R(0), R(0)}, ga[3] = {R(0), R(0), R(0)}, pa[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+      R ea = R(0), gs = R(0);
+      static_for<Q>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr double x0 = S::xh(q, 0), x1 = S::xh(q, 1), x2 = S::xh(q, 2);
+        constexpr double X = x0 * x0 + x1 * x1 + x2 * x2;
+        const R d = ft[q][r], e = ft[Q + q][r];
+        if constexpr (X != 0.0) ea = fma(R(X), d, ea);
+        gs += e;
+        if constexpr (x0 != 0.0) { qa[0] = fma(R(x0 * X), d, qa[0]); ga[0] = fma(R(x0), e, ga[0]); pa[0] = fma(R(x0 * x0), d, pa[0]); }
+        if constexpr (x1 != 0.0) { qa[1] = fma(R(x1 * X), d, qa[1]); ga[1] = fma(R(x1), e, ga[1]); pa[1] = fma(R(x1 * x1), d, pa[1]); }
+        if constexpr (x2 != 0.0) { qa[2] = fma(R(x2 * X), d, qa[2]); ga[2] = fma(R(x2), e, ga[2]); pa[2] = fma(R(x2 * x2), d, pa[2]); }
+        if constexpr (x0 * x1 != 0.0) pa[3] = fma(R(x0 * x1), d, pa[3]);
+        if constexpr (x0 * x2 != 0.0) pa[4] = fma(R(x0 * x2), d, pa[4]);
+        if constexpr (x1 * x2 != 0.0) pa[5] = fma(R(x1 * x2), d, pa[5]);
+      });
+      const R rho_ = m.rho, th = m.theta;
+      const R u[3] = {m.ux, m.uy, m.uz};
+      // rho theta less the reference the sums exclude (deviations: 1)
+      const R rt = DEV ? fma(rho_, m.eta, m.dr) : rho_ * th;
+      const R cv2r = R(p.cv2mD);
+      const R trp = ea - rho_ * m.U - R(D) * rt;
+      R pn[3][3];
+      const int pi[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) pn[a][b] = pa[pi[a][b]] - rho_ * u[a] * u[b] - (a == b ? rt : R(0));
+      const R gneq = gs - cv2r * rt;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        R qn = qa[a] - rho_ * u[a] * (m.U + R(D + 2) * th);
+        qn -= R(2) * (pn[a][0] * u[0] + pn[a][1] * u[1] + pn[a][2] * u[2]);
+        qn -= u[a] * trp;
+        m.qf[a] = (a < D) ? qn : R(0);
+        m.qg[a] = (a < D) ? ga[a] - cv2r * th * rho_ * u[a] - u[a] * gneq : R(0);
+      }
+      // tau_q = 1/2 + (tau - 1/2) / Pr
+      m.omq = R(1) / (R(0.5) + R(p.tau_m_half * p.inv_pr) / (rho_ * th));
+    }
     (void)Ef; (void)G; (void)Ed;
     return m;
   };
 
-  if constexpr (MODE == MODE_STEP) {
+  // xh_q . q_g: the g quasi-equilibrium's term is w_q times this
+  auto qe_g = [&](auto qc, const Mom& m) -> R {
+    constexpr int q = decltype(qc)::value;
+    R ag = R(0);
+    if constexpr (S::moves(q, 0)) ag = fma(R(S::xh(q, 0)), m.qg[0], ag);
+    if constexpr (S::moves(q, 1)) ag = fma(R(S::xh(q, 1)), m.qg[1], ag);
+    if constexpr (D == 3 && S::moves(q, 2)) ag = fma(R(S::xh(q, 2)), m.qg[2], ag);
+    return ag;
+  };
+  (void)qe_g;
+
+  if constexpr (is_step(MODE)) {
     Mom mc[RO];
 #pragma unroll
     for (int r = 0; r < RO; ++r) mc[r] = moments(r);
@@ -1418,7 +1483,16 @@ void sl_kernel(KParams p) {
         R df = feq_dev - ft[q][r];
         if constexpr (DEV && X != 0.0) df = fma(w * (m.rho * R(p.cmom1)), a, df);
         if constexpr (EFIX) df = fma(w, cM[r], df);
-        const R fo = fma(m.omega, df, ft[q][r]);
+        R fo = fma(m.omega, df, ft[q][r]);
+        if constexpr (MODE == MODE_STEP_QE) {
+          // + (omega - omega_q)(f* - f^eq): the quasi-equilibrium's heat-flux term
+          constexpr double kf = S::w(q) * (X - (D + 2)) / (2.0 * (D + 2));
+          R aq = R(0);
+          if constexpr (S::moves(q, 0)) aq = fma(R(S::xh(q, 0)), m.qf[0], aq);
+          if constexpr (S::moves(q, 1)) aq = fma(R(S::xh(q, 1)), m.qf[1], aq);
+          if constexpr (D == 3 && S::moves(q, 2)) aq = fma(R(S::xh(q, 2)), m.qf[2], aq);
+          fo = fma((m.omega - m.omq) * R(kf), aq, fo);
+        }
         put_at(q, r, SUBREF ? fo + w : fo);
         if constexpr (COMP) {
           R geq;
@@ -1430,7 +1504,8 @@ void sl_kernel(KParams p) {
             if (p.e64 != 0.0) Eeq64[r] += X * double(feq_dev) + double(geq);
             ft[q][r] = geq - ft[Q + q][r];  // f_q is stored: its register keeps g^eq - g
           } else {
-            const R go = fma(m.omega, geq - ft[Q + q][r], ft[Q + q][r]);
+            R go = fma(m.omega, geq - ft[Q + q][r], ft[Q + q][r]);
+            if constexpr (MODE == MODE_STEP_QE) go = fma((m.omega - m.omq) * w, qe_g(qc, m), go);
             put_at(Q + q, r, SUBREF ? go + cv2 * w : go);
           }
         }
@@ -1449,7 +1524,8 @@ void sl_kernel(KParams p) {
 #pragma unroll
         for (int r = 0; r < RO; ++r) {
           if (D == 2 && r >= ovalid) break;
-          const R go = fma(mc[r].omega, fma(w, cE[r], ft[q][r]), ft[Q + q][r]);
+          R go = fma(mc[r].omega, fma(w, cE[r], ft[q][r]), ft[Q + q][r]);
+          if constexpr (MODE == MODE_STEP_QE) go = fma((mc[r].omega - mc[r].omq) * w, qe_g(qc, mc[r]), go);
           put_at(Q + q, r, SUBREF ? go + cv2 * w : go);
         }
       });
