@@ -18,9 +18,30 @@ inline void host_for(F&& f) {
   host_for_impl(f, std::make_integer_sequence<int, N>{});
 }
 
+// Blocks of one sl_kernel instantiation that fit on a compute unit at once.
+template <int SET, int NS, int N, int A, int ST, int MODE, int CP, int XP>
+int blocks_per_cu() {
+  using TL = Tile<SET, NS, A, ST, cells_per_thread<Set<SET>::D, Set<SET>::Q, A, ST, MODE>()>;
+  static const int per_cu = [] {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&sl_kernel<SET, NS, N, A, ST, MODE, CP, XP>),
+                                                     TL::NT, 0) != hipSuccess || nb < 1)
+      nb = 1;
+    return nb;
+  }();
+  return per_cu;
+}
+
+// Whether a kernel interpolates along x through LDS at all (3D with a stencil
+// longer than one node): only those have the single-load variant XP = 0.
+template <int SET, int NS>
+constexpr bool has_x_pairs() {
+  return Set<SET>::D == 3 && NS > 1;
+}
+
 template <int SET, int NS, int N, int A, int ST, int MODE, int CP = 0>
 hipError_t launch_step(const KParams& p, hipStream_t s) {
-  using R = typename StoreT<ST>::real;
+  using E = typename StoreT<ST>::elem;
   constexpr int D = Set<SET>::D;
   constexpr int RO = cells_per_thread<D, Set<SET>::Q, A, ST, MODE>();
   using TL = Tile<SET, NS, A, ST, RO>;
@@ -33,6 +54,16 @@ hipError_t launch_step(const KParams& p, hipStream_t s) {
     q.tiles[1] = (p.n[1] + TL::NW * RO - 1) / (TL::NW * RO);
     q.tiles[2] = 1;
   }
+  // x pairs in one two-element load: x periodic with nx even (a pair never
+  // straddles the wrap or a row end) and every buffer the interpolation reads
+  // aligned to two elements
+  auto al2 = [](const void* ptr) { return reinterpret_cast<uintptr_t>(ptr) % (2 * sizeof(E)) == 0; };
+  constexpr bool reads_src = MODE != MODE_ADJ_STREAM;
+  constexpr bool reads_src2 = MODE == MODE_ADJ_STEP || MODE == MODE_ADJ_STREAM;
+  const bool pairs = p.bc[0] == 0 && (p.n[0] & 1) == 0 && (p.pstride & 1) == 0 && (!reads_src || al2(p.src)) &&
+                     (!reads_src2 || al2(p.src2));
+  const int per_cu = (has_x_pairs<SET, NS>() && !pairs) ? blocks_per_cu<SET, NS, N, A, ST, MODE, CP, 0>()
+                                                         : blocks_per_cu<SET, NS, N, A, ST, MODE, CP, 1>();
   const int64_t ntiles = int64_t(q.tiles[0]) * q.tiles[1] * q.tiles[2];
   q.chunk = int((ntiles + 7) / 8);
   q.rsy = q.rsz = 0;
@@ -47,13 +78,6 @@ hipError_t launch_step(const KParams& p, hipStream_t s) {
     // state and 12 % faster, FP32 4.2x -> 2.9x at equal time; with two cells
     // per thread (the 16-bit kernels) the x, y, z order reads less
     // (2.6x against 3.9x) and runs 2 % faster, so they keep it.
-    static const int per_cu = [] {
-      int nb = 0;
-      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&sl_kernel<SET, NS, N, A, ST, MODE, CP>),
-                                                       TL::NT, 0) != hipSuccess || nb < 1)
-        nb = 1;
-      return nb;
-    }();
     const int window = per_cu * (p.cus > 0 ? p.cus / 8 : 32);
     if (RO == 1 && 2 * q.tiles[0] * q.rsy > window) {
       q.bz = std::min(q.rsz, 16);
@@ -65,7 +89,13 @@ hipError_t launch_step(const KParams& p, hipStream_t s) {
     }
   }
   const dim3 grid(unsigned(q.chunk) * 8u);
-  hipLaunchKernelGGL((sl_kernel<SET, NS, N, A, ST, MODE, CP>), grid, dim3(TL::NT), 0, s, q);
+  if constexpr (has_x_pairs<SET, NS>()) {
+    if (!pairs) {
+      hipLaunchKernelGGL((sl_kernel<SET, NS, N, A, ST, MODE, CP, 0>), grid, dim3(TL::NT), 0, s, q);
+      return hipGetLastError();
+    }
+  }
+  hipLaunchKernelGGL((sl_kernel<SET, NS, N, A, ST, MODE, CP, 1>), grid, dim3(TL::NT), 0, s, q);
   return hipGetLastError();
 }
 

@@ -407,7 +407,17 @@ struct PopIn {
 // (off, wts).  With SUB every loaded value has ref[a] subtracted (exact for
 // values within a factor two of the reference), so the interpolation works
 // on deviations.
-template <int SET, int NS, int A, int ST, int RO, int q, bool SUB>
+//
+// XP (3D populations through LDS): 1 loads each pair of x nodes with one
+// two-element load, valid when the launch has x periodic, nx even and
+// buffers aligned to two elements (then a pair never straddles the wrap or a
+// row end); 0 loads the two nodes singly (clamped x, odd nx, unaligned
+// buffers).  Either way every lane issues the same loads with no branch:
+// lanes past the last column repeat it.  A branch around the loads (per lane
+// or per launch) makes the compiler wait for every load in flight, the next
+// population's included, before the first use of any of them, which undoes
+// the software pipeline below.
+template <int SET, int NS, int A, int ST, int RO, int q, bool SUB, int XP>
 __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>::elem* __restrict__ src,
                                          int64_t pstride, const int* __restrict__ off,
                                          const typename StoreT<ST>::real* __restrict__ wts,
@@ -423,13 +433,13 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
   constexpr int HX = PS::HX, HM = PS::HM, HO = PS::HO;
   constexpr int axm = 1, axo = D - 1;
 
-  // x and y offsets through the axis representatives: populations with the
-  // same (x, y) components then share their per-lane column addresses
-  constexpr int qx = axis_rep<SET, 0>(q), qm = axis_rep<SET, axm>(q);
+  // offsets through the axis representatives: populations with the same
+  // component share their per-lane column addresses and scalar row offsets
+  constexpr int qx = axis_rep<SET, 0>(q), qm = axis_rep<SET, axm>(q), qo = axis_rep<SET, axo>(q);
   const cptr<int> offc = as_const(off);
   const int ox = offc[3 * qx + 0];
   const int om = (D == 3) ? offc[3 * qm + axm] : 0;
-  const int oo = offc[3 * q + axo];
+  const int oo = offc[3 * qo + axo];
 
   const E* base[A];
 #pragma unroll
@@ -446,8 +456,7 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
   };
 
   int col[PS::ROUNDS], ob[PS::ROUNDS], vo[PS::ROUNDS];
-  int col2[PS::ROUNDS];   // X2: column of the pair's second node
-  bool pair[PS::ROUNDS];  // X2: the pair is one aligned two-element load
+  int col2[PS::ROUNDS];  // X2 with single loads: column of the pair's second node
   in.sh = 0;
   if constexpr (PS::direct) {
     // each thread loads its own column
@@ -466,25 +475,26 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
     const int xs0 = g.x0 + ox;
     const int xa = g.x0 + (ox & ~1);
     in.sh = ox & 1;
-    const int xlim = xs0 + g.vx + HX;  // one node beyond the last one the stencil needs
-    // pairs start at even element offsets: aligned when the array base and the
-    // population stride are (and nx is even, which makes every row even)
-    const bool aligned2 = (g.nx & 1) == 0 && (pstride & 1) == 0 &&
-                          (reinterpret_cast<uintptr_t>(src) % (2 * sizeof(E))) == 0;
+    // one node beyond the last one the stencil needs: the nodes of the
+    // columns past it (a partial tile) are never read
+    const int xlim = xs0 + g.vx + HX;
 #pragma unroll
     for (int rr = 0; rr < PS::ROUNDS; ++rr) {
       const int c = min(g.tid + TL::NT * rr, PS::NCOL - 1);
       const int j = c % PS::CX, ms = c / PS::CX;
       in.slot[rr] = ms * TL::PX + 2 * j;
       const int e0 = max(min(xa + 2 * j, xlim), -g.nx), e1 = max(min(xa + 2 * j + 1, xlim), -g.nx);
-      col[rr] = wrap_idx(min(e0, 2 * g.nx - 1), g.nx, g.bcx);
-      col2[rr] = wrap_idx(min(e1, 2 * g.nx - 1), g.nx, g.bcx);
       const int cm = wrap_idx(g.m0 + om + min(ms, g.vm - 1 + HM), g.nm, g.bcm) * g.sm;
-      // one two-element load when the pair is adjacent in memory and aligned;
-      // else two single loads (clamped x boundary, odd nx, unaligned buffer)
-      pair[rr] = aligned2 && col2[rr] == col[rr] + 1;
-      col[rr] += cm;
-      col2[rr] += cm;
+      if constexpr (XP) {
+        // periodic x, nx even: xa + 2j wraps to an even node whose successor
+        // is the pair's second node; a start clamped at xlim (unread) is
+        // rounded down to its pair
+        col[rr] = (wrap_idx(min(e0, 2 * g.nx - 1), g.nx, 0) & ~1) + cm;
+        col2[rr] = col[rr] + 1;
+      } else {
+        col[rr] = wrap_idx(min(e0, 2 * g.nx - 1), g.nx, g.bcx) + cm;
+        col2[rr] = wrap_idx(min(e1, 2 * g.nx - 1), g.nx, g.bcx) + cm;
+      }
     }
   } else {
 #pragma unroll
@@ -512,46 +522,34 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
   }
   if constexpr (PS::X2) {
 #pragma unroll
-    for (int rr = 0; rr < PS::ROUNDS; ++rr) {
-      if (PS::NCOL % TL::NT == 0 || rr + 1 < PS::ROUNDS || g.tid + TL::NT * rr < PS::NCOL) {
-        if (pair[rr]) {
+    for (int rr = 0; rr < PS::ROUNDS; ++rr)
 #pragma unroll
-          for (int r = 0; r < RO + HO; ++r) {
-            const int row = row_at(g.o0, g.vo, r);
+      for (int r = 0; r < RO + HO; ++r) {
+        const int row = row_at(g.o0, g.vo, r);
 #pragma unroll
-            for (int a = 0; a < A; ++a)
-              TR::ldb2(rs[a], boff<E>(col[rr]), boff<E>(row), in.v[rr][a][r][0], in.v[rr][a][r][1]);
-          }
-        } else {
-#pragma unroll
-          for (int r = 0; r < RO + HO; ++r) {
-            const int row = row_at(g.o0, g.vo, r);
-#pragma unroll
-            for (int a = 0; a < A; ++a) {
-              in.v[rr][a][r][0] = TR::ldb(rs[a], boff<E>(col[rr]), boff<E>(row));
-              in.v[rr][a][r][1] = TR::ldb(rs[a], boff<E>(col2[rr]), boff<E>(row));
-            }
+        for (int a = 0; a < A; ++a) {
+          if constexpr (XP) {
+            TR::ldb2(rs[a], boff<E>(col[rr]), boff<E>(row), in.v[rr][a][r][0], in.v[rr][a][r][1]);
+          } else {
+            in.v[rr][a][r][0] = TR::ldb(rs[a], boff<E>(col[rr]), boff<E>(row));
+            in.v[rr][a][r][1] = TR::ldb(rs[a], boff<E>(col2[rr]), boff<E>(row));
           }
         }
       }
-    }
   } else {
 #pragma unroll
-    for (int rr = 0; rr < PS::ROUNDS; ++rr) {
-      if (PS::direct || PS::NCOL % TL::NT == 0 || rr + 1 < PS::ROUNDS || g.tid + TL::NT * rr < PS::NCOL) {
+    for (int rr = 0; rr < PS::ROUNDS; ++rr)
 #pragma unroll
-        for (int r = 0; r < RO + HO; ++r) {
-          const int row = row_at(ob[rr], vo[rr], r);
+      for (int r = 0; r < RO + HO; ++r) {
+        const int row = row_at(ob[rr], vo[rr], r);
 #pragma unroll
-          for (int a = 0; a < A; ++a) {
-            if constexpr (D == 3)
-              in.v[rr][a][r][0] = TR::ldb(rs[a], boff<E>(col[rr]), boff<E>(row));
-            else
-              in.v[rr][a][r][0] = TR::ld(at(base[a], row + col[rr]));
-          }
+        for (int a = 0; a < A; ++a) {
+          if constexpr (D == 3)
+            in.v[rr][a][r][0] = TR::ldb(rs[a], boff<E>(col[rr]), boff<E>(row));
+          else
+            in.v[rr][a][r][0] = TR::ld(at(base[a], row + col[rr]));
         }
       }
-    }
   }
   if constexpr (SUB) {
 #pragma unroll
@@ -587,12 +585,15 @@ struct PopW {
     bx = 0;
     bm[0] = 0;
     if constexpr (!G) {
+      // the weights along an axis depend on the velocity component only: read
+      // them at the axis representative, so that populations share the loads
+      constexpr int qx = axis_rep<SET, 0>(q), qm = axis_rep<SET, axm>(q), qo = axis_rep<SET, axo>(q);
 #pragma unroll
-      for (int k = 0; k < PS::KX; ++k) wx[k] = PS::mx ? wc[(3 * q + 0) * NS + k] : R(1);
+      for (int k = 0; k < PS::KX; ++k) wx[k] = PS::mx ? wc[(3 * qx + 0) * NS + k] : R(1);
 #pragma unroll
-      for (int k = 0; k < PS::KM; ++k) wm[0][k] = PS::mm ? wc[(3 * q + axm) * NS + k] : R(1);
+      for (int k = 0; k < PS::KM; ++k) wm[0][k] = PS::mm ? wc[(3 * qm + axm) * NS + k] : R(1);
 #pragma unroll
-      for (int k = 0; k < PS::KO; ++k) wo[0][k] = PS::mo ? wc[(3 * q + axo) * NS + k] : R(1);
+      for (int k = 0; k < PS::KO; ++k) wo[0][k] = PS::mo ? wc[(3 * qo + axo) * NS + k] : R(1);
     } else {
       constexpr int XE = PS::SP::xent, W = PS::SP::win;
       if constexpr (PS::mx) {
@@ -672,20 +673,18 @@ __device__ __forceinline__ void stage_A(const Geo& g, PopIn<SET, NS, A, ST, RO, 
   if constexpr (PS::direct) {
     outer(in.v[0], 0, out);
   } else {
+    // lanes past the last column repeat it: the same value to the same slot
 #pragma unroll
-    for (int rr = 0; rr < PS::ROUNDS; ++rr) {
-      if (PS::NCOL % TL::NT == 0 || rr + 1 < PS::ROUNDS || g.tid + TL::NT * rr < PS::NCOL) {
+    for (int rr = 0; rr < PS::ROUNDS; ++rr)
 #pragma unroll
-        for (int k = 0; k < XW; ++k) {
-          R res[A][RO];
-          outer(in.v[rr], k, res);
+      for (int k = 0; k < XW; ++k) {
+        R res[A][RO];
+        outer(in.v[rr], k, res);
 #pragma unroll
-          for (int a = 0; a < A; ++a)
+        for (int a = 0; a < A; ++a)
 #pragma unroll
-            for (int r = 0; r < RO; ++r) P[(a * RO + r) * PM * PX + in.slot[rr] + k] = res[a][r];
-        }
+          for (int r = 0; r < RO; ++r) P[(a * RO + r) * PM * PX + in.slot[rr] + k] = res[a][r];
       }
-    }
   }
 }
 
@@ -848,7 +847,7 @@ constexpr int lds_rank() {  // number of LDS-using populations before q
 // Tile::TSZ; consecutive users of LDS alternate between buffers so that a
 // population's stage A never overwrites what a lagging wave still reads.
 // `sink(q, out)` receives each result.
-template <int SET, int NS, int A, int ST, int RO, bool SUB, int PARITY, int GROUP = 1>
+template <int SET, int NS, int A, int ST, int RO, bool SUB, int PARITY, int GROUP, int XP>
 struct Pipe {
   using R = typename StoreT<ST>::real;
   using E = typename StoreT<ST>::elem;
@@ -867,7 +866,7 @@ struct Pipe {
                                               PopIn<SET, NS, A, ST, RO, q>& in) {
     R ref[A];
     refs(q, cv2, ref);
-    pop_load<SET, NS, A, ST, RO, q, SUB>(g, src, pstride, off, wts, ref, in);
+    pop_load<SET, NS, A, ST, RO, q, SUB, XP>(g, src, pstride, off, wts, ref, in);
   }
 
   template <int q, class Sink>
@@ -1050,8 +1049,9 @@ constexpr int sl_min_waves() {
           cells_per_thread<Set<SET>::D, Set<SET>::Q, A, ST, MODE>() == 1) ? 4 : 1;
 }
 
-// CP: cache policy of the result stores (0 or CP_STREAM).
-template <int SET, int NS, int N, int A, int ST, int MODE, int CP = 0>
+// CP: cache policy of the result stores (0 or CP_STREAM).  XP: x pairs
+// loaded with one two-element load (1) or singly (0), see pop_load.
+template <int SET, int NS, int N, int A, int ST, int MODE, int CP, int XP>
 __global__ __launch_bounds__((sl_threads<SET, NS, A, ST, MODE>()), (sl_min_waves<SET, NS, A, ST, MODE>()))
 void sl_kernel(KParams p) {
   using S = Set<SET>;
@@ -1164,7 +1164,7 @@ void sl_kernel(KParams p) {
   const R cv2 = R(p.cv2mD);
 
   if constexpr (MODE != MODE_ADJ_STREAM) {
-    Pipe<SET, NS, A, ST, RO, SUBREF, 0, GROUP>::all(g, src, p.pstride, p.off, wts, cv2, &P_lds[0][0],
+    Pipe<SET, NS, A, ST, RO, SUBREF, 0, GROUP, XP>::all(g, src, p.pstride, p.off, wts, cv2, &P_lds[0][0],
                                                             &T_lds[0][0], [&](auto qc, R (&o)[A][RO]) {
       constexpr int q = decltype(qc)::value;
 #pragma unroll
@@ -1177,9 +1177,9 @@ void sl_kernel(KParams p) {
     // S^T applied to src2 with the transposed stencil; src2 is of the compute type
     const E* __restrict__ src2 = static_cast<const E*>(p.src2);
     constexpr int parity =
-        (MODE == MODE_ADJ_STREAM) ? 0 : Pipe<SET, NS, A, ST, RO, SUBREF, 0, GROUP>::next_parity();
+        (MODE == MODE_ADJ_STREAM) ? 0 : Pipe<SET, NS, A, ST, RO, SUBREF, 0, GROUP, XP>::next_parity();
     static_assert(MODE == MODE_ADJ_STREAM || A == 1, "adjoint kernels are built for one array");
-    Pipe<SET, NS, 1, ST, RO, false, parity>::all(g, src2, p.pstride, p.off_t, wts_t, cv2, &P_lds[0][0],
+    Pipe<SET, NS, 1, ST, RO, false, parity, 1, XP>::all(g, src2, p.pstride, p.off_t, wts_t, cv2, &P_lds[0][0],
                                                   &T_lds[0][0], [&](auto qc, R (&o)[1][RO]) {
       constexpr int q = decltype(qc)::value;
 #pragma unroll

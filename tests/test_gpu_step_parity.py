@@ -72,10 +72,16 @@ def test_reduced_precision_weak_sets_one_step(orc, name, storage):
     plus the rounding of the result; 2^-23 more for FP16's subnormals)."""
     order = 3 if name == "D3V27" else 2
     lat, got, ref = problem(orc, name, storage, n=4, order=order, steps=1)
+    check16(lat, got, ref, storage, "weak16_%s_%s" % (name, storage))
+
+
+def check16(lat, got, ref, storage, case):
+    """One step of 16-bit storage: each value within three units of the
+    format's roundoff of its population's largest deviation from w_i."""
     r = reference_values(lat).reshape((-1, 1, 1, 1))
     scale = np.max(np.abs(ref - r), axis=(1, 2, 3), keepdims=True)
     tol = 3 * ULP[storage] * scale + 2.0 ** -23
-    note("weak16_%s_%s" % (name, storage), err=float(np.max(np.abs(got - ref) / tol)))
+    note(case, err=float(np.max(np.abs(got - ref) / tol)))
     assert np.all(np.abs(got - ref) <= tol), float(np.max(np.abs(got - ref) / tol))
 
 
@@ -125,20 +131,26 @@ def test_minimal_grid(orc, name, storage, comp):
     check(lat, got, ref, storage, "minimal_%s_%s" % (name, storage), factor=3 if comp else 1)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "f16"])
 @pytest.mark.parametrize("grid,bc", [((67, 9, 6), (0, 0, 0)), ((70, 9, 6), (1, 0, 0))])
 def test_x_pair_load_fallbacks(orc, storage, grid, bc):
-    """3D populations load x in pairs of adjacent nodes; an odd nx (pairs not
-    aligned) and a clamped x boundary (pairs not adjacent) take single loads."""
+    """3D populations load x in pairs of adjacent nodes when x is periodic
+    with nx even; an odd nx (a pair would straddle the wrap) and a clamped x
+    boundary (pairs not adjacent) launch the single-load kernels."""
     name = "D3Q27"
     cs = 0.6
     dt = 0.45 / (W.MAX_COMPONENT_OVER_CS[name] * cs)
     lat, cfg = pair(orc, name, grid, tau=0.57, order=2, n=4, storage=storage, dx=1.0, dt=dt, cs=cs, bc=bc)
     rho, u, _ = W.random_fields(3, cfg.shape, 5, u_amp=0.1 * cs, rho_amp=0.02)
     f0 = init_both(lat, orc, cfg, rho, u)
-    lat.step(2)
-    ref = orc.run(cfg, f0, 2)
-    check(lat, gpu_populations(lat), ref, storage, "xpair_%s_%s" % (storage, "".join(map(str, bc))))
+    steps = 1 if storage in ULP else 2
+    lat.step(steps)
+    ref = orc.run(cfg, f0, steps)
+    case = "xpair_%s_%s_%d" % (storage, "".join(map(str, bc)), grid[0])
+    if storage in ULP:
+        check16(lat, gpu_populations(lat), ref, storage, case)
+    else:
+        check(lat, gpu_populations(lat), ref, storage, case)
 
 
 @pytest.mark.parametrize("name,storage,bc,n,comp", [
@@ -169,10 +181,10 @@ def test_extrapolating_axes(orc, name, storage, bc, n, comp):
           factor=3 if comp else 1)
 
 
-@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16", "f16"])
 def test_unaligned_buffers_match_aligned(orc, storage):
-    """Buffers starting one element off an even address take the single-load
-    path; the step is the same to the last bit."""
+    """Buffers starting one element off an even address launch the
+    single-load kernels; the step is the same to the last bit."""
     import torch
 
     name = "D3Q21"
@@ -192,7 +204,7 @@ def test_unaligned_buffers_match_aligned(orc, storage):
     src.copy_(f0)
     lat.step_into(src, dst)
     torch.cuda.synchronize()
-    ints = torch.int64 if storage == "f64" else torch.int32
+    ints = {"f64": torch.int64, "f32": torch.int32}.get(storage, torch.int16)
     assert torch.equal(dst.view(ints), out_a.view(ints))
 
 
