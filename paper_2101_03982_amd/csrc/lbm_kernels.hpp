@@ -391,6 +391,17 @@ struct PopShape {
   static_assert(!X2 || 2 * CX <= TL::PX, "LDS row too short for the pair window");
 };
 
+// Whether lanes past the last column of a partial round skip it with a branch
+// rather than repeating the last column.  The branch costs the software
+// pipeline (see pop_load), repeating costs the round's loads and stage A work.
+// 2D tiles (68 load columns per 64-lane row at n = 5: a last round 6 % full)
+// measured 13-17 % faster with the branch in FP64 storage and equal or 4-6 %
+// slower in FP32; 3D rounds are full or nearly so.
+template <int D, int ST>
+constexpr bool skip_round_tail() {
+  return D == 2 && ST == ST_F64;
+}
+
 // Everything population q needs after its loads were issued: the loaded
 // values (still in flight until first use) and where each round's column
 // lands in LDS.
@@ -413,10 +424,10 @@ struct PopIn {
 // buffers aligned to two elements (then a pair never straddles the wrap or a
 // row end); 0 loads the two nodes singly (clamped x, odd nx, unaligned
 // buffers).  Either way every lane issues the same loads with no branch:
-// lanes past the last column repeat it.  A branch around the loads (per lane
-// or per launch) makes the compiler wait for every load in flight, the next
-// population's included, before the first use of any of them, which undoes
-// the software pipeline below.
+// lanes past the last column repeat it (2D FP64 aside, skip_round_tail).  A
+// branch around the loads (per lane or per launch) makes the compiler wait
+// for every load in flight, the next population's included, before the first
+// use of any of them, which undoes the software pipeline (Pipe).
 template <int SET, int NS, int A, int ST, int RO, int q, bool SUB, int XP>
 __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>::elem* __restrict__ src,
                                          int64_t pstride, const int* __restrict__ off,
@@ -537,8 +548,10 @@ __device__ __forceinline__ void pop_load(const Geo& g, const typename StoreT<ST>
         }
       }
   } else {
+    constexpr bool SKIP = skip_round_tail<D, ST>() && !PS::direct && PS::NCOL % TL::NT != 0;
 #pragma unroll
     for (int rr = 0; rr < PS::ROUNDS; ++rr)
+      if (!SKIP || rr + 1 < PS::ROUNDS || g.tid + TL::NT * rr < PS::NCOL)
 #pragma unroll
       for (int r = 0; r < RO + HO; ++r) {
         const int row = row_at(ob[rr], vo[rr], r);
@@ -673,9 +686,12 @@ __device__ __forceinline__ void stage_A(const Geo& g, PopIn<SET, NS, A, ST, RO, 
   if constexpr (PS::direct) {
     outer(in.v[0], 0, out);
   } else {
-    // lanes past the last column repeat it: the same value to the same slot
+    // lanes past the last column repeat it (the same value to the same slot)
+    // or skip it (skip_round_tail)
+    constexpr bool SKIP = skip_round_tail<PS::D, ST>() && PS::NCOL % TL::NT != 0;
 #pragma unroll
     for (int rr = 0; rr < PS::ROUNDS; ++rr)
+      if (!SKIP || rr + 1 < PS::ROUNDS || g.tid + TL::NT * rr < PS::NCOL)
 #pragma unroll
       for (int k = 0; k < XW; ++k) {
         R res[A][RO];
