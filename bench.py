@@ -160,6 +160,7 @@ def adjoint_cost(n=64, steps=200, every=20):
         t2 = time.perf_counter()
         times.append((t1 - t0, t2 - t1))
     fwd, bwd = min(times, key=lambda t: t[0] + t[1])
+    g32 = u0.grad.detach().double()
     # plain forward without checkpoints, for reference
     lat.init_equilibrium(rho, torch.from_numpy(u_np).to("cuda:0", torch.float32))
     torch.cuda.synchronize()
@@ -167,9 +168,21 @@ def adjoint_cost(n=64, steps=200, every=20):
     lat.step(steps)
     torch.cuda.synchronize()
     plain = time.perf_counter() - t0
+    lat.close()
+    # the same gradient in FP64: the FP32 gradient's deviation from it
+    wl64 = W.adjoint_workload(n=n, steps=steps, storage="f64")
+    lat64 = Lattice(wl64.set, wl64.grid, wl64.tau, wl64.order, stencil=wl64.stencil, storage="f64", dx=wl64.dx,
+                    dt=wl64.dt, cs=wl64.cs, device="cuda:0")
+    u64 = torch.from_numpy(u_np).to("cuda:0", torch.float64).requires_grad_(True)
+    kinetic_energy_after(u64, torch.from_numpy(rho_np).to("cuda:0", torch.float64), lat64, steps,
+                         every=every).backward()
+    g64 = u64.grad.detach()
+    lat64.close()
     return {"workload": "D3Q27 %d^3 FP32, %d steps, checkpoints every %d, loss = final kinetic energy" % (
         n, steps, every), "forward_s": fwd, "backward_s": bwd, "plain_forward_s": plain,
-        "adjoint_over_forward": bwd / fwd, "adjoint_over_plain_forward": bwd / plain}
+        "adjoint_over_forward": bwd / fwd, "adjoint_over_plain_forward": bwd / plain,
+        "fp32_grad_rel_l2_vs_fp64": float(torch.linalg.norm(g32 - g64) / torch.linalg.norm(g64)),
+        "fp32_grad_max_rel_vs_fp64": float(torch.max(torch.abs(g32 - g64)) / torch.max(torch.abs(g64)))}
 
 
 def dissipation(sets=SETS, n=128, t_end=1.5625, logs=40):

@@ -10,14 +10,14 @@
 * The differentiation workload (D3Q27, 64^3, 200 steps, checkpoints every 20,
   loss = final kinetic energy, TGV plus N(0, 1e-3^2) perturbation): directional
   derivatives against central finite differences on 16 random directions,
-  FP64, within 1e-6; the FP32 gradient's deviation is bounded too.
+  FP64, within 1e-6; the FP32 gradient within 5e-5 of the FP64 one.
 """
 import numpy as np
 import pytest
 import torch
 
 import lbm_inputs as W
-from gpu_helpers import init_both, pair, rel_err, to_dev
+from gpu_helpers import init_both, note, pair, rel_err, to_dev
 from paper_2101_03982_amd import Lattice, kinetic_energy_after
 
 pytestmark = pytest.mark.gpu
@@ -123,4 +123,10 @@ def test_fp32_gradient_close_to_fp64():
     g64, _ = _fd_check("f64", ndir=0)
     g32, _ = _fd_check("f32", ndir=0)
     err = float(torch.linalg.norm(g32 - g64) / torch.linalg.norm(g64))
-    assert err < 1e-2, err
+    worst = float(torch.max(torch.abs(g32 - g64)) / torch.max(torch.abs(g64)))
+    note("adjoint_fp32_vs_fp64", rel_l2=err, max_rel=worst)
+    # FP32 deviation storage rounds each step's populations to ~3e-8 of their
+    # scale; over 200 forward and 200 reverse steps that is ~1e-5 (measured
+    # 1.1e-5 rel. L2, 1.3e-5 worst element against the largest)
+    assert err < 5e-5, err
+    assert worst < 5e-5, worst
