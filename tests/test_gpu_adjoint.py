@@ -27,9 +27,10 @@ def dev_state(lat, a):
     return to_dev(a, lat.dtype).reshape(lat.pop_shape).contiguous()
 
 
-@pytest.mark.parametrize("name", ["D3Q27", "D3Q21", "D2Q19"])
-def test_stream_transpose_dot_product(orc, name):
-    grid = (66, 9, 7) if W.DIM[name] == 3 else (70, 21, 1)
+@pytest.mark.parametrize("name,nx", [("D3Q27", 66), ("D3Q21", 66), ("D2Q19", 70), ("D3Q27", 67)])
+def test_stream_transpose_dot_product(orc, name, nx):
+    """An odd nx launches the single-load x variant of the 3D kernels."""
+    grid = (nx, 9, 7) if W.DIM[name] == 3 else (nx, 21, 1)
     lat, cfg = pair(orc, name, grid, 0.6, 2, 4, "f64", dt=0.4)
     rng = np.random.default_rng(0)
     v = dev_state(lat, rng.normal(size=cfg.pop_shape()))
@@ -45,9 +46,11 @@ def test_stream_transpose_dot_product(orc, name):
     assert rel_err(STw.cpu().numpy(), orc.stream_transpose(cfg, w.cpu().numpy())) < 1e-13
 
 
-@pytest.mark.parametrize("name,order", [("D3Q27", 2), ("D3V27", 2), ("D2Q9", 2), ("D3Q45", 2)])
-def test_adjoint_kernels_vs_oracle(orc, name, order):
-    grid = (66, 9, 7) if W.DIM[name] == 3 else (70, 21, 1)
+@pytest.mark.parametrize("name,order,nx", [("D3Q27", 2, 66), ("D3V27", 2, 66), ("D2Q9", 2, 70), ("D3Q45", 2, 66),
+                                           ("D3Q27", 2, 67)])
+def test_adjoint_kernels_vs_oracle(orc, name, order, nx):
+    """nx = 67: the single-load x variant of the adjoint kernels."""
+    grid = (nx, 9, 7) if W.DIM[name] == 3 else (nx, 21, 1)
     cs = 0.6
     dt = 0.4 / (W.MAX_COMPONENT_OVER_CS[name] * cs)
     lat, cfg = pair(orc, name, grid, 0.57, order, 4, "f64", dt=dt, cs=cs)
