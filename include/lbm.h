@@ -99,6 +99,18 @@ typedef enum lbm_boundary {
   LBM_EXTRAPOLATE = 1   /* zeroth-order extrapolation: indices clamp to the edge */
 } lbm_boundary;
 
+/* How 16-bit storage rounds each stored value. */
+typedef enum lbm_rounding {
+  LBM_ROUND_NEAREST = 0,    /* to nearest, ties to even (default) */
+  LBM_ROUND_STOCHASTIC = 1  /* LBM_BF16DEV only (LBM_EUNSUPPORTED otherwise): up or down with
+                               probabilities given by the distance to the two neighbouring
+                               values, so the rounding error has mean zero.  The random bits are
+                               a hash of the cell, the array, the context's count of steps
+                               taken and `seed`: a run repeats exactly from the same state,
+                               step count and seed.  Not a method of the paper: a storage
+                               choice of this library's reduced-precision form. */
+} lbm_rounding;
+
 typedef struct lbm_options {
   int32_t storage;       /* lbm_storage */
   int32_t stencil;       /* Lagrange nodes per axis n, 1..5 (LBM_GLC: p + 1 points per cell edge) */
@@ -119,6 +131,8 @@ typedef struct lbm_options {
                             design notes), every other moment at 1/tau.  Built for D3Q45 with
                             n = 4 and D2Q19 / D2Q25 with n = 5, LBM_F64 / LBM_F32 storage
                             (LBM_EUNSUPPORTED otherwise). */
+  int32_t rounding;      /* lbm_rounding of the stored values (default LBM_ROUND_NEAREST) */
+  uint32_t seed;         /* LBM_ROUND_STOCHASTIC: seed of the random bits */
 } lbm_options;
 
 typedef struct lbm_diag {
@@ -316,7 +330,7 @@ int lbm_float_moment_defects(int32_t set, double *out);
 const char *lbm_strerror(int status);
 const char *lbm_last_error(void);
 
-/* Version of the ABI described by this header. */
+/* Version of the ABI described by this header (3: lbm_options.rounding and seed). */
 int32_t lbm_abi_version(void);
 
 #ifdef __cplusplus

@@ -15,6 +15,7 @@ SETS = ("D2Q9", "D2Q19", "D2Q25", "D3Q13", "D3Q21", "D3Q27", "D3V27", "D3Q45")
 STORAGES = ("f64", "f32", "bf16", "f16")
 BOUNDARIES = ("periodic", "extrapolate")
 SUPPORTS = ("uniform", "glc")
+ROUNDINGS = ("nearest", "stochastic")
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EHIP, LBM_EUNSUPPORTED, LBM_EDIVERGED = 0, -1, -2, -3, -4, -5
 
@@ -33,6 +34,8 @@ class Options(ctypes.Structure):
         ("gamma", ctypes.c_double),
         ("stream", ctypes.c_void_p),
         ("prandtl", ctypes.c_double),
+        ("rounding", ctypes.c_int32),
+        ("seed", ctypes.c_uint32),
     ]
 
 

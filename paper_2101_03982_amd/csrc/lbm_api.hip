@@ -191,6 +191,9 @@ struct lbm_ctx {
   int glc_p = 0;            // cell-wise support: cell order p (0: uniform support)
   int cus = 0;              // compute units of the device
   double prandtl = 1.0;     // compressible model: Prandtl number (1: plain BGK)
+  int rounding = LBM_ROUND_NEAREST;  // how 16-bit storage rounds
+  uint32_t seed = 0;        // stochastic rounding: seed of the random bits
+  uint64_t nstep = 0;       // steps the context has taken (stochastic rounding's counter)
   double* d_partial = nullptr;
   double* d_result = nullptr;
   double* h_result = nullptr;
@@ -522,7 +525,7 @@ int launch(hipError_t e, const char* what) { return e == hipSuccess ? LBM_OK : h
 
 extern "C" {
 
-int32_t lbm_abi_version(void) { return 2; }
+int32_t lbm_abi_version(void) { return 3; }
 
 const char* lbm_strerror(int status) {
   switch (status) {
@@ -690,6 +693,11 @@ int lbm_create(lbm_ctx** out, int32_t set, const int64_t grid[3], double tau, in
   }
   if (!find_kernels(set, c->ns, order, c->A, c->storage, &c->k))
     return bad(LBM_EUNSUPPORTED, "no kernel built for this set / stencil / order / model / storage");
+  if (o.rounding != LBM_ROUND_NEAREST && o.rounding != LBM_ROUND_STOCHASTIC) return bad(LBM_EINVAL, "unknown rounding");
+  if (o.rounding == LBM_ROUND_STOCHASTIC && c->storage != LBM_BF16DEV)
+    return bad(LBM_EUNSUPPORTED, "stochastic rounding applies to BF16 storage");
+  c->rounding = o.rounding;
+  c->seed = o.seed;
   if (!(o.prandtl > 0) || !std::isfinite(o.prandtl)) return bad(LBM_EINVAL, "the Prandtl number must be positive");
   c->prandtl = o.prandtl;
   if (c->prandtl != 1.0 && !c->k.step_qe)
@@ -850,10 +858,21 @@ int lbm_set_state(lbm_ctx* c, const void* src) {
 // the halo rows that neighbouring tiles re-read.
 constexpr size_t LLC_BYTES = size_t(256) << 20;
 
+// Per-step seed of stochastic rounding: the context's seed and step count
+// through SplitMix64's finalizer (a published 64-bit mixer).
+static uint32_t step_seed(uint32_t seed, uint64_t step) {
+  uint64_t z = (uint64_t(seed) << 32 | (step & 0xffffffffu)) + 0x9e3779b97f4a7c15ull * (step >> 32);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return uint32_t((z ^ (z >> 31)) >> 32);
+}
+
 static int step_once(lbm_ctx* c, const void* src, void* dst) {
   KParams p = base_params(c);
   p.src = src;
   p.dst = dst;
+  p.sr = c->rounding == LBM_ROUND_STOCHASTIC ? 1 : 0;
+  p.seed = step_seed(c->seed, c->nstep++);
   const bool big = 2 * c->state_bytes > LLC_BYTES;
   StepLaunch f = (c->k.step_stream && big) ? c->k.step_stream : c->k.mode[MODE_STEP];
   if (c->prandtl != 1.0) f = (c->k.step_qe_stream && big) ? c->k.step_qe_stream : c->k.step_qe;

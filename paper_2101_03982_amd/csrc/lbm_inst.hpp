@@ -89,9 +89,24 @@ hipError_t launch_step(const KParams& p, hipStream_t s) {
     }
   }
   const dim3 grid(unsigned(q.chunk) * 8u);
+  // stochastic rounding: its own instantiation of the BF16 step kernels
+  constexpr bool has_sr = ST == ST_BF16 && MODE == MODE_STEP;
+  const bool sr = has_sr && p.sr != 0;
   if constexpr (has_x_pairs<SET, NS>()) {
     if (!pairs) {
+      if constexpr (has_sr) {
+        if (sr) {
+          hipLaunchKernelGGL((sl_kernel<SET, NS, N, A, ST, MODE, CP, 0, 1>), grid, dim3(TL::NT), 0, s, q);
+          return hipGetLastError();
+        }
+      }
       hipLaunchKernelGGL((sl_kernel<SET, NS, N, A, ST, MODE, CP, 0>), grid, dim3(TL::NT), 0, s, q);
+      return hipGetLastError();
+    }
+  }
+  if constexpr (has_sr) {
+    if (sr) {
+      hipLaunchKernelGGL((sl_kernel<SET, NS, N, A, ST, MODE, CP, 1, 1>), grid, dim3(TL::NT), 0, s, q);
       return hipGetLastError();
     }
   }

@@ -55,6 +55,26 @@ __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
   return uint16_t(u >> 16);
 }
 
+// stochastic rounding: 16 uniform random bits added below the kept ones, then
+// truncation; rounds the magnitude up with probability equal to the dropped
+// fraction of a unit in the last place, so the error has mean zero.  NaN stays NaN.
+__device__ __forceinline__ uint16_t f32_to_bf16_sr(float f, uint32_t rnd) {
+  const uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
+  return uint16_t((u + (rnd & 0xffffu)) >> 16);
+}
+
+// Wellons' 32-bit integer hash ("lowbias32": two multiply-xorshift rounds), the
+// random bits of stochastic rounding.
+__device__ __forceinline__ uint32_t hash32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
 // dev: the kernels compute on deviations d = f - r from the reference values
 //      r_i = w_i (f) and (2 C_v - D) w_i (g), which keeps rounding relative to
 //      the small deviations instead of the populations;
@@ -135,6 +155,12 @@ template <> struct StoreT<ST_BF16> {
   static __device__ __forceinline__ void stb(real v, rsrc_t r, int voff, int soff) {
     __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16(v), r, voff, soff, CP);
   }
+  // stochastic rounding with random bits rnd
+  template <int CP = 0>
+  static __device__ __forceinline__ void stb_sr(real v, uint32_t rnd, rsrc_t r, int voff, int soff) {
+    __builtin_amdgcn_raw_buffer_store_b16(f32_to_bf16_sr(v, rnd), r, voff, soff, CP);
+  }
+  static __device__ __forceinline__ void st_sr(elem* p, real v, uint32_t rnd) { *p = f32_to_bf16_sr(v, rnd); }
   static __device__ __forceinline__ void ldb2(rsrc_t r, int voff, int soff, real& lo, real& hi) {
     const unsigned v = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
     lo = bf16_to_f32(uint16_t(v & 0xffffu));
@@ -240,6 +266,8 @@ struct KParams {
   // FP32 compressible model: defects of the FP32-rounded set's moments against
   // the Gaussian ones (MASS_* layout below), for the mass restoration
   double mdef[30];
+  uint32_t seed;       // stochastic rounding: this launch's seed
+  int sr;              // nonzero: BF16 step stores round stochastically (host: selects the RND variant)
 };
 
 // Layout of KParams::mdef: [0] sum w - 1; [1..6] quadratic, [8..13]
@@ -1066,8 +1094,10 @@ constexpr int sl_min_waves() {
 }
 
 // CP: cache policy of the result stores (0 or CP_STREAM).  XP: x pairs
-// loaded with one two-element load (1) or singly (0), see pop_load.
-template <int SET, int NS, int N, int A, int ST, int MODE, int CP, int XP>
+// loaded with one two-element load (1) or singly (0), see pop_load.  RND:
+// BF16 step stores round to nearest (0) or stochastically (1; a variant of its
+// own, so that the default keeps its code size and schedule).
+template <int SET, int NS, int N, int A, int ST, int MODE, int CP, int XP, int RND = 0>
 __global__ __launch_bounds__((sl_threads<SET, NS, A, ST, MODE>()), (sl_min_waves<SET, NS, A, ST, MODE>()))
 void sl_kernel(KParams p) {
   using S = Set<SET>;
@@ -1232,6 +1262,17 @@ void sl_kernel(KParams p) {
     return (D == 3) ? (r < ovalid ? boff<E>((obase + r) * g.so) : boff<E>(int(p.pstride))) : 0;
   };
   auto put_at = [&](int k, int r, R v) {  // store array k (population, or Q + population) of cell r
+    if constexpr (RND) {  // stochastic rounding, bits from (cell, array, seed)
+      static_assert(ST == ST_BF16 && is_step(MODE), "stochastic rounding: BF16 step kernels");
+      const uint32_t cell = uint32_t((D == 3) ? (obase + r) * g.so + lc_of(r) : lc_of(r));
+      const uint32_t rnd = hash32((cell * uint32_t(A * Q) + uint32_t(k)) ^ p.seed);
+      if constexpr (D == 3)
+        TR::template stb_sr<CP>(v, rnd, make_rsrc(dst + int64_t(k) * p.pstride, p.pstride), boff<E>(lc_of(r)),
+                                rowb_of(r));
+      else
+        TR::st_sr(at(dst + int64_t(k) * p.pstride, lc_of(r)), v, rnd);
+      return;
+    }
     if constexpr (D == 3)
       TR::template stb<CP>(v, make_rsrc(dst + int64_t(k) * p.pstride, p.pstride), boff<E>(lc_of(r)), rowb_of(r));
     else

@@ -44,7 +44,8 @@ class Lattice:
     def __init__(self, set: str, grid, tau: float, order: int = 2, *, stencil: int = 4, storage: str = "f32",
                  dx: float = 1.0, dt: float = 1.0, cs: float = 0.0, compressible: bool = False,
                  gamma: float = 1.4, boundary=("periodic", "periodic", "periodic"), energy_f64: bool = False,
-                 support: str = "uniform", prandtl: float = 1.0, device=None):
+                 support: str = "uniform", prandtl: float = 1.0, rounding: str = "nearest", seed: int = 0,
+                 device=None):
         if set not in _Q:
             raise ValueError("unknown velocity set %r" % (set,))
         if storage not in _STATE_DTYPE:
@@ -76,6 +77,9 @@ class Lattice:
         self.support = support
         opt.prandtl = float(prandtl)
         self.prandtl = float(prandtl)
+        opt.rounding = _lib.ROUNDINGS.index(rounding)
+        opt.seed = int(seed) & 0xFFFFFFFF
+        self.rounding = rounding
         opt.dx, opt.dt, opt.cs, opt.gamma = self.dx, self.dt, float(cs), self.gamma
         with torch.cuda.device(self.device):
             opt.stream = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)

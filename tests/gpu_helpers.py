@@ -15,11 +15,12 @@ BC = {0: "periodic", 1: "extrapolate"}
 
 
 def pair(orc, set_, grid, tau, order=2, n=4, storage="f64", dx=1.0, dt=1.0, cs=0.0, compressible=False,
-         gamma=1.4, bc=(0, 0, 0), energy_f64=False, support="uniform", prandtl=1.0):
-    """(GPU lattice, oracle config) of the same problem."""
+         gamma=1.4, bc=(0, 0, 0), energy_f64=False, support="uniform", prandtl=1.0, rounding="nearest", seed=0):
+    """(GPU lattice, oracle config) of the same problem (rounding and seed:
+    the GPU's storage only)."""
     lat = Lattice(set_, grid, tau, order, stencil=n, storage=storage, dx=dx, dt=dt, cs=cs,
                   compressible=compressible, gamma=gamma, boundary=tuple(BC[b] for b in bc), energy_f64=energy_f64,
-                  support=support, prandtl=prandtl, device="cuda:0")
+                  support=support, prandtl=prandtl, rounding=rounding, seed=seed, device="cuda:0")
     cfg = orc.Config(set_, tuple(grid) + (1,) * (3 - len(grid)), tau=tau, order=order, stencil=n, dx=dx, dt=dt,
                      cs=cs, compressible=compressible, gamma=gamma, bc=bc, kind=support, prandtl=prandtl)
     return lat, cfg

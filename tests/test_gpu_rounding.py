@@ -1,0 +1,91 @@
+"""Stochastic rounding of BF16 storage (lbm_options.rounding): not a method of
+the paper but a storage choice of the reduced-precision form.
+
+* One step from the equilibrium against the FP64 oracle, each stored value
+  within three units of BF16's roundoff of its population's largest
+  deviation from w_i (the bound of the round-to-nearest kernels; stochastic
+  rounding errs by less than one unit).
+* Against round to nearest from the same state: every stored value equal or
+  one unit away, and about a quarter of them one unit away (the probability
+  of rounding away from the nearest value, averaged over uniformly placed
+  values, is 1/4).
+* The random bits depend on the cell, the array, the step count and the seed
+  only: equal seeds repeat a run bit for bit, different seeds differ.
+"""
+import numpy as np
+import pytest
+import torch
+
+import lbm_inputs as W
+from gpu_helpers import gpu_populations, init_both, note, pair, reference_values, to_dev
+from paper_2101_03982_amd import Lattice
+
+pytestmark = pytest.mark.gpu
+
+ULP = 2.0 ** -8
+
+
+def _lattice(name, comp, rounding, seed=0, grid=(70, 13, 7)):
+    cs = 0.6
+    dt = 0.45 / (W.MAX_COMPONENT_OVER_CS[name] * cs)
+    order = 4 if comp else 2
+    return Lattice(name, grid, 0.57, order, stencil=4, storage="bf16", dx=1.0, dt=dt, cs=cs, compressible=comp,
+                   rounding=rounding, seed=seed, device="cuda:0"), dt, cs, order
+
+
+def _init(lat, comp, seed=3):
+    D = 3
+    rho, u, theta = W.random_fields(D, lat.shape, seed, u_amp=0.06, rho_amp=0.02, theta_amp=0.03 if comp else 0.0)
+    lat.init_equilibrium(to_dev(rho, torch.float32), to_dev(u, torch.float32),
+                         to_dev(theta, torch.float32) if comp else None)
+    return rho, u, theta
+
+
+@pytest.mark.parametrize("name,comp", [("D3Q27", False), ("D3Q45", True)])
+def test_stochastic_one_step_parity(orc, name, comp):
+    cs = 0.6
+    dt = 0.45 / (W.MAX_COMPONENT_OVER_CS[name] * cs)
+    order = 4 if comp else 2
+    lat, cfg = pair(orc, name, (70, 13, 7), tau=0.57, order=order, n=4, storage="bf16", dx=1.0, dt=dt, cs=cs,
+                    compressible=comp, rounding="stochastic", seed=11)
+    rho, u, theta = W.random_fields(3, cfg.shape, 0, u_amp=0.1 * cs, rho_amp=0.02, theta_amp=0.03 if comp else 0.0)
+    f0 = init_both(lat, orc, cfg, rho, u, theta if comp else None)
+    lat.step(1)
+    ref = orc.run(cfg, f0, 1)
+    got = gpu_populations(lat)
+    r = reference_values(lat).reshape((-1, 1, 1, 1))
+    scale = np.max(np.abs(ref - r), axis=(1, 2, 3), keepdims=True)
+    tol = 3 * ULP * scale + 2.0 ** -23
+    note("sr_%s" % name, err=float(np.max(np.abs(got - ref) / tol)))
+    assert np.all(np.abs(got - ref) <= tol), float(np.max(np.abs(got - ref) / tol))
+
+
+@pytest.mark.parametrize("name,comp", [("D3Q27", False), ("D3Q45", True)])
+def test_stochastic_against_nearest(name, comp):
+    a, *_ = _lattice(name, comp, "nearest")
+    b, *_ = _lattice(name, comp, "stochastic", seed=5)
+    for lat in (a, b):
+        _init(lat, comp)
+        lat.step(1)
+    torch.cuda.synchronize()
+    ia = a.state().view(torch.int16).to(torch.int32)
+    ib = b.state().view(torch.int16).to(torch.int32)
+    # BF16 values of one sign are ordered as their bit patterns: adjacent
+    # values differ by one in the pattern (zero is approached from both sides)
+    diff = (ib - ia).abs()
+    same_sign = (ia >= 0) == (ib >= 0)
+    assert int(diff[same_sign].max()) <= 1
+    frac = float((diff > 0).double().mean())
+    note("sr_frac_%s" % name, frac=frac)
+    assert 0.15 < frac < 0.35, frac
+
+
+def test_stochastic_repeats_with_its_seed():
+    lats = [_lattice("D3Q27", False, "stochastic", seed=s)[0] for s in (7, 7, 8)]
+    for lat in lats:
+        _init(lat, False)
+        lat.step(3)
+    torch.cuda.synchronize()
+    s0, s1, s2 = (lat.state().view(torch.int16) for lat in lats)
+    assert torch.equal(s0, s1)
+    assert not torch.equal(s0, s2)

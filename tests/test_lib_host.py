@@ -39,7 +39,7 @@ def test_exports_every_declared_symbol(L):
 
 def test_abi_and_strerror(L):
     lib = L.lib()
-    assert lib.lbm_abi_version() == 2
+    assert lib.lbm_abi_version() == 3
     for code in (0, -1, -2, -3, -4, -5):
         assert lib.lbm_strerror(code)
     assert lib.lbm_strerror(-99) == b"unknown status"
@@ -142,6 +142,9 @@ def _create(L, set_id, grid, tau=0.8, order=2, **opt):
     ((7, (8, 8, 8), 0.8, 4, {"compressible": 1, "prandtl": 0.75, "stencil": 3}), -4),  # ... n = 4 for D3Q45
     ((7, (8, 8, 8), 0.8, 4, {"compressible": 1, "prandtl": 0.75, "storage": 2}), -4),  # ... FP64/FP32
     ((7, (8, 8, 8), 0.8, 4, {"compressible": 1, "prandtl": 0.0}), -1),                 # Pr > 0
+    ((5, (8, 8, 8), 0.8, 2, {"rounding": 1}), -4),                      # stochastic rounding: BF16 only
+    ((5, (8, 8, 8), 0.8, 2, {"rounding": 1, "storage": 3}), -4),        # ... not FP16
+    ((5, (8, 8, 8), 0.8, 2, {"rounding": 2, "storage": 2}), -1),        # unknown rounding
 ])
 def test_create_rejects(L, args, code):
     set_id, grid = args[0], args[1]
