@@ -22,18 +22,15 @@ struct CurlParams {
   double* partial;
 };
 
-// i wrapped onto a periodic line of N nodes, for i within a few lines of
-// [0, N) (stencil offsets of at most MAX_HALF_WIDTH plus a tile's extent):
-// adds or subtracts N instead of an integer division, which on the GPU is a
-// long instruction sequence that the lanes at every tile's edge would run.
-__device__ inline int64_t wrap_any(int64_t i, int64_t N) {
-  while (i < 0) i += N;
-  while (i >= N) i -= N;
-  return i;
-}
-
 // Index of i + d on a periodic line of N nodes, |d| <= MAX_HALF_WIDTH.
-__device__ inline int64_t wrap(int64_t i, int d, int64_t N) { return wrap_any(i + d, N); }
+__device__ inline int64_t wrap(int64_t i, int d, int64_t N) {
+  int64_t k = i + d;
+  if (k >= N || k < 0) {
+    k %= N;
+    if (k < 0) k += N;
+  }
+  return k;
+}
 
 // Central difference of field f along the line through node `row + i*stride`
 // (row = the node's index with its coordinate along this axis set to 0).
@@ -86,6 +83,12 @@ __global__ __launch_bounds__(DIAG_THREADS) void enstrophy2d_kernel(CurlParams p)
 // wrapped onto the periodic grid; lanes past a ragged edge load wrapped
 // nodes and add nothing.
 constexpr int ZT_X = 64, ZT_Y = DIAG_WAVES, ZT_Z = 4;
+
+__device__ inline int64_t wrap_any(int64_t i, int64_t N) {
+  if (i >= 0 && i < N) return i;
+  i %= N;
+  return i < 0 ? i + N : i;
+}
 
 template <typename R, int M>
 __global__ __launch_bounds__(DIAG_THREADS) void enstrophy3d_kernel(CurlParams p) {
