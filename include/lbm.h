@@ -106,8 +106,9 @@ typedef enum lbm_rounding {
                                probabilities given by the distance to the two neighbouring
                                values, so the rounding error has mean zero.  The random bits are
                                a hash of the cell, the array, the context's count of steps
-                               taken and `seed`: a run repeats exactly from the same state,
-                               step count and seed.  Not a method of the paper: a storage
+                               taken (every lbm_step step and lbm_step_into call advances it)
+                               and `seed`: a run repeats exactly from the same state, step
+                               count and seed.  Not a method of the paper: a storage
                                choice of this library's reduced-precision form. */
 } lbm_rounding;
 
