@@ -287,10 +287,11 @@ def high_mach(n=256, t_end=10.0, machs=(0.5, 1.0, 1.5, 2.0), storage="f32", ever
     return res
 
 
-def precision_form(n=256, steps=1000, machs=(0.5, 1.0), storages=("f64", "f32", "bf16", "bf16_sr", "f16")):
+def precision_form(n=256, steps=1000, machs=(0.5, 1.0),
+                   storages=("f64", "f32", "bf16", "bf16_sr", "f16", "f16_sr")):
     """Compressible TGV with D3Q45 (N = 4, n = 4): time per step and error
-    after `steps` steps of the BF16/FP16 deviation storage (bf16_sr: BF16 with
-    stochastic rounding) and of FP32 against the FP64 run on the same GPU."""
+    after `steps` steps of the BF16/FP16 deviation storage (*_sr: stochastic
+    rounding) and of FP32 against the FP64 run on the same GPU."""
     import numpy as np
     import torch
 
@@ -304,11 +305,11 @@ def precision_form(n=256, steps=1000, machs=(0.5, 1.0), storages=("f64", "f32", 
         ref = None
         entry = {}
         for st in storages:
-            sto = "bf16" if st == "bf16_sr" else st
+            sto = st[:-3] if st.endswith("_sr") else st
             lat = Lattice("D3Q45", wl.grid, wl.tau, 4, stencil=wl.stencil, storage=sto, dx=wl.dx, dt=wl.dt,
                           cs=wl.cs, compressible=True, gamma=wl.gamma,
                           energy_f64=(sto in ("bf16", "f16") and Ma >= 1.0),
-                          rounding="stochastic" if st == "bf16_sr" else "nearest", device="cuda:0")
+                          rounding="stochastic" if st.endswith("_sr") else "nearest", device="cuda:0")
             dt_ = lat.dtype
             lat.init_equilibrium(torch.from_numpy(rho_np).to("cuda:0", dt_), torch.from_numpy(u_np).to("cuda:0", dt_),
                                  torch.from_numpy(th_np).to("cuda:0", dt_))
@@ -346,7 +347,7 @@ def precision_form(n=256, steps=1000, machs=(0.5, 1.0), storages=("f64", "f32", 
             lat.close()
             del lat
             torch.cuda.empty_cache()
-        for st in ("bf16", "bf16_sr", "f16"):
+        for st in ("bf16", "bf16_sr", "f16", "f16_sr"):
             if "f32" in entry and st in entry:
                 entry["speedup_%s_over_f32" % st] = entry["f32"]["ms_per_step"] / entry[st]["ms_per_step"]
         res["Ma%.1f" % Ma] = entry

@@ -102,7 +102,7 @@ typedef enum lbm_boundary {
 /* How 16-bit storage rounds each stored value. */
 typedef enum lbm_rounding {
   LBM_ROUND_NEAREST = 0,    /* to nearest, ties to even (default) */
-  LBM_ROUND_STOCHASTIC = 1  /* LBM_BF16DEV only (LBM_EUNSUPPORTED otherwise): up or down with
+  LBM_ROUND_STOCHASTIC = 1  /* 16-bit storage (LBM_EUNSUPPORTED otherwise): up or down with
                                probabilities given by the distance to the two neighbouring
                                values, so the rounding error has mean zero.  The random bits are
                                a hash of the cell, the array, the context's count of steps

@@ -694,8 +694,8 @@ int lbm_create(lbm_ctx** out, int32_t set, const int64_t grid[3], double tau, in
   if (!find_kernels(set, c->ns, order, c->A, c->storage, &c->k))
     return bad(LBM_EUNSUPPORTED, "no kernel built for this set / stencil / order / model / storage");
   if (o.rounding != LBM_ROUND_NEAREST && o.rounding != LBM_ROUND_STOCHASTIC) return bad(LBM_EINVAL, "unknown rounding");
-  if (o.rounding == LBM_ROUND_STOCHASTIC && c->storage != LBM_BF16DEV)
-    return bad(LBM_EUNSUPPORTED, "stochastic rounding applies to BF16 storage");
+  if (o.rounding == LBM_ROUND_STOCHASTIC && c->storage != LBM_BF16DEV && c->storage != LBM_F16DEV)
+    return bad(LBM_EUNSUPPORTED, "stochastic rounding applies to 16-bit storage");
   c->rounding = o.rounding;
   c->seed = o.seed;
   if (!(o.prandtl > 0) || !std::isfinite(o.prandtl)) return bad(LBM_EINVAL, "the Prandtl number must be positive");

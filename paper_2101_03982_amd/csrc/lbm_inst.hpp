@@ -89,8 +89,8 @@ hipError_t launch_step(const KParams& p, hipStream_t s) {
     }
   }
   const dim3 grid(unsigned(q.chunk) * 8u);
-  // stochastic rounding: its own instantiation of the BF16 step kernels
-  constexpr bool has_sr = ST == ST_BF16 && MODE == MODE_STEP;
+  // stochastic rounding: its own instantiation of the 16-bit step kernels
+  constexpr bool has_sr = (ST == ST_BF16 || ST == ST_F16) && MODE == MODE_STEP;
   const bool sr = has_sr && p.sr != 0;
   if constexpr (has_x_pairs<SET, NS>()) {
     if (!pairs) {

@@ -1,10 +1,10 @@
-"""Stochastic rounding of BF16 storage (lbm_options.rounding): not a method of
-the paper but a storage choice of the reduced-precision form.
+"""Stochastic rounding of 16-bit storage (lbm_options.rounding): not a method
+of the paper but a storage choice of the reduced-precision form.
 
 * One step from the equilibrium against the FP64 oracle, each stored value
-  within three units of BF16's roundoff of its population's largest
+  within three units of the format's roundoff of its population's largest
   deviation from w_i (the bound of the round-to-nearest kernels; stochastic
-  rounding errs by less than one unit).
+  rounding errs by less than one unit; 2^-23 more for FP16's subnormals).
 * Against round to nearest from the same state: every stored value equal or
   one unit away, and about a quarter of them one unit away (the probability
   of rounding away from the nearest value, averaged over uniformly placed
@@ -22,14 +22,14 @@ from paper_2101_03982_amd import Lattice
 
 pytestmark = pytest.mark.gpu
 
-ULP = 2.0 ** -8
+ULP = {"bf16": 2.0 ** -8, "f16": 2.0 ** -11}
 
 
-def _lattice(name, comp, rounding, seed=0, grid=(70, 13, 7)):
+def _lattice(name, comp, rounding, seed=0, grid=(70, 13, 7), storage="bf16"):
     cs = 0.6
     dt = 0.45 / (W.MAX_COMPONENT_OVER_CS[name] * cs)
     order = 4 if comp else 2
-    return Lattice(name, grid, 0.57, order, stencil=4, storage="bf16", dx=1.0, dt=dt, cs=cs, compressible=comp,
+    return Lattice(name, grid, 0.57, order, stencil=4, storage=storage, dx=1.0, dt=dt, cs=cs, compressible=comp,
                    rounding=rounding, seed=seed, device="cuda:0"), dt, cs, order
 
 
@@ -41,12 +41,13 @@ def _init(lat, comp, seed=3):
     return rho, u, theta
 
 
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
 @pytest.mark.parametrize("name,comp", [("D3Q27", False), ("D3Q45", True)])
-def test_stochastic_one_step_parity(orc, name, comp):
+def test_stochastic_one_step_parity(orc, name, comp, storage):
     cs = 0.6
     dt = 0.45 / (W.MAX_COMPONENT_OVER_CS[name] * cs)
     order = 4 if comp else 2
-    lat, cfg = pair(orc, name, (70, 13, 7), tau=0.57, order=order, n=4, storage="bf16", dx=1.0, dt=dt, cs=cs,
+    lat, cfg = pair(orc, name, (70, 13, 7), tau=0.57, order=order, n=4, storage=storage, dx=1.0, dt=dt, cs=cs,
                     compressible=comp, rounding="stochastic", seed=11)
     rho, u, theta = W.random_fields(3, cfg.shape, 0, u_amp=0.1 * cs, rho_amp=0.02, theta_amp=0.03 if comp else 0.0)
     f0 = init_both(lat, orc, cfg, rho, u, theta if comp else None)
@@ -55,33 +56,35 @@ def test_stochastic_one_step_parity(orc, name, comp):
     got = gpu_populations(lat)
     r = reference_values(lat).reshape((-1, 1, 1, 1))
     scale = np.max(np.abs(ref - r), axis=(1, 2, 3), keepdims=True)
-    tol = 3 * ULP * scale + 2.0 ** -23
-    note("sr_%s" % name, err=float(np.max(np.abs(got - ref) / tol)))
+    tol = 3 * ULP[storage] * scale + 2.0 ** -23
+    note("sr_%s_%s" % (name, storage), err=float(np.max(np.abs(got - ref) / tol)))
     assert np.all(np.abs(got - ref) <= tol), float(np.max(np.abs(got - ref) / tol))
 
 
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
 @pytest.mark.parametrize("name,comp", [("D3Q27", False), ("D3Q45", True)])
-def test_stochastic_against_nearest(name, comp):
-    a, *_ = _lattice(name, comp, "nearest")
-    b, *_ = _lattice(name, comp, "stochastic", seed=5)
+def test_stochastic_against_nearest(name, comp, storage):
+    a, *_ = _lattice(name, comp, "nearest", storage=storage)
+    b, *_ = _lattice(name, comp, "stochastic", seed=5, storage=storage)
     for lat in (a, b):
         _init(lat, comp)
         lat.step(1)
     torch.cuda.synchronize()
     ia = a.state().view(torch.int16).to(torch.int32)
     ib = b.state().view(torch.int16).to(torch.int32)
-    # BF16 values of one sign are ordered as their bit patterns: adjacent
+    # 16-bit values of one sign are ordered as their bit patterns: adjacent
     # values differ by one in the pattern (zero is approached from both sides)
     diff = (ib - ia).abs()
     same_sign = (ia >= 0) == (ib >= 0)
     assert int(diff[same_sign].max()) <= 1
     frac = float((diff > 0).double().mean())
-    note("sr_frac_%s" % name, frac=frac)
+    note("sr_frac_%s_%s" % (name, storage), frac=frac)
     assert 0.15 < frac < 0.35, frac
 
 
-def test_stochastic_repeats_with_its_seed():
-    lats = [_lattice("D3Q27", False, "stochastic", seed=s)[0] for s in (7, 7, 8)]
+@pytest.mark.parametrize("storage", ["bf16", "f16"])
+def test_stochastic_repeats_with_its_seed(storage):
+    lats = [_lattice("D3Q27", False, "stochastic", seed=s, storage=storage)[0] for s in (7, 7, 8)]
     for lat in lats:
         _init(lat, False)
         lat.step(3)

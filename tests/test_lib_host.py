@@ -142,8 +142,8 @@ def _create(L, set_id, grid, tau=0.8, order=2, **opt):
     ((7, (8, 8, 8), 0.8, 4, {"compressible": 1, "prandtl": 0.75, "stencil": 3}), -4),  # ... n = 4 for D3Q45
     ((7, (8, 8, 8), 0.8, 4, {"compressible": 1, "prandtl": 0.75, "storage": 2}), -4),  # ... FP64/FP32
     ((7, (8, 8, 8), 0.8, 4, {"compressible": 1, "prandtl": 0.0}), -1),                 # Pr > 0
-    ((5, (8, 8, 8), 0.8, 2, {"rounding": 1}), -4),                      # stochastic rounding: BF16 only
-    ((5, (8, 8, 8), 0.8, 2, {"rounding": 1, "storage": 3}), -4),        # ... not FP16
+    ((5, (8, 8, 8), 0.8, 2, {"rounding": 1}), -4),                      # stochastic rounding: 16-bit only
+    ((5, (8, 8, 8), 0.8, 2, {"rounding": 1, "storage": 0}), -4),        # ... not FP64
     ((5, (8, 8, 8), 0.8, 2, {"rounding": 2, "storage": 2}), -1),        # unknown rounding
 ])
 def test_create_rejects(L, args, code):
