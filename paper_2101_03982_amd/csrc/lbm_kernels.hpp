@@ -83,7 +83,8 @@ __device__ __forceinline__ uint32_t hash32(uint32_t x) {
 //      r_i = w_i (f) and (2 C_v - D) w_i (g), which keeps rounding relative to
 //      the small deviations instead of the populations;
 // stores_dev: the buffer itself holds deviations (all but FP64);
-// kahan: moment sums with compensated summation.
+// coarse: 16-bit storage, whose rounding lies far above the FP32 arithmetic's:
+//      no energy restoration in the collision; optional FP64 energy sum.
 // ldb/stb: buffer accesses at byte offset voff (per lane) + soff (uniform,
 // scalar register), so that a row offset shared by the block costs no vector
 // instruction.  The resource covers one population array (< 4 GiB).  stb's
@@ -108,7 +109,7 @@ __device__ __forceinline__ rsrc_t make_rsrc(const E* base, int64_t nelem) {
 template <int S> struct StoreT;
 template <> struct StoreT<ST_F64> {
   using elem = double; using real = double;
-  static constexpr bool dev = false, stores_dev = false, kahan = false;
+  static constexpr bool dev = false, stores_dev = false, coarse = false;
   static __device__ __forceinline__ real ld(const elem* p) { return *p; }
   static __device__ __forceinline__ void st(elem* p, real v) { *p = v; }
   static __device__ __forceinline__ real ldb(rsrc_t r, int voff, int soff) {
@@ -130,7 +131,7 @@ template <> struct StoreT<ST_F64> {
 };
 template <> struct StoreT<ST_F32> {
   using elem = float; using real = float;
-  static constexpr bool dev = true, stores_dev = true, kahan = false;
+  static constexpr bool dev = true, stores_dev = true, coarse = false;
   static __device__ __forceinline__ real ld(const elem* p) { return *p; }
   static __device__ __forceinline__ void st(elem* p, real v) { *p = v; }
   static __device__ __forceinline__ real ldb(rsrc_t r, int voff, int soff) {
@@ -149,7 +150,7 @@ template <> struct StoreT<ST_F32> {
 };
 template <> struct StoreT<ST_BF16> {
   using elem = uint16_t; using real = float;
-  static constexpr bool dev = true, stores_dev = true, kahan = true;
+  static constexpr bool dev = true, stores_dev = true, coarse = true;
   static __device__ __forceinline__ real ld(const elem* p) { return bf16_to_f32(*p); }
   static __device__ __forceinline__ void st(elem* p, real v) { *p = f32_to_bf16(v); }
   static __device__ __forceinline__ real ldb(rsrc_t r, int voff, int soff) {
@@ -173,7 +174,7 @@ template <> struct StoreT<ST_BF16> {
 };
 template <> struct StoreT<ST_F16> {
   using elem = _Float16; using real = float;
-  static constexpr bool dev = true, stores_dev = true, kahan = true;
+  static constexpr bool dev = true, stores_dev = true, coarse = true;
   static __device__ __forceinline__ real ld(const elem* p) { return float(*p); }
   static __device__ __forceinline__ void st(elem* p, real v) { *p = _Float16(v); }
   static __device__ __forceinline__ void st_sr(elem* p, real v, uint32_t rnd) { *p = f32_to_f16_sr(v, rnd); }
@@ -1074,17 +1075,6 @@ __device__ __forceinline__ void peq_derivs(R a, R U, R& P, R& Pa, R& PU) {
   }
 }
 
-template <typename R>
-struct Kahan {
-  R s = R(0), c = R(0);
-  __device__ __forceinline__ void add(R v) {
-    R y = v - c;
-    R t = s + y;
-    c = (t - s) - y;
-    s = t;
-  }
-};
-
 // ---------------------------------------------------------------------------
 // The fused kernel
 // ---------------------------------------------------------------------------
@@ -1308,59 +1298,48 @@ void sl_kernel(KParams p) {
     // equilibrium is formed in (deviations, or whole values for FP64)
     R Epre = R(0);
     double Epre64 = 0.0;
-    if constexpr (DEV && TR::kahan) {
-      Kahan<R> kr, kx, ky, kz, ke, kg;
-      static_for<Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        const R d = ft[q][r];
-        kr.add(d);
-        if constexpr (S::moves(q, 0)) kx.add(R(S::xh(q, 0)) * d);
-        if constexpr (S::moves(q, 1)) ky.add(R(S::xh(q, 1)) * d);
-        if constexpr (D == 3 && S::moves(q, 2)) kz.add(R(S::xh(q, 2)) * d);
-        if constexpr (COMP) {
-          constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
-          if (p.e64 != 0.0) Ed = fma(X, double(d), Ed);
-          else ke.add(R(X) * d);
-          kg.add(ft[Q + q][r]);
-        }
-      });
-      drho = R(p.sw - 1.0) + kr.s;
-      rho = R(p.sw) + kr.s;
-      jx = R(p.swx[0]) + kx.s;
-      jy = R(p.swx[1]) + ky.s;
-      jz = R(p.swx[2]) + kz.s;
-      if constexpr (COMP) {
-        Epre64 = Ed + double(kg.s);
-        Epre = ke.s + kg.s;
-        Ed += p.swX;
-        Ef = R(p.swX) + ke.s;
-        G = R(p.cv2mD * p.sw) + kg.s;
-      }
-    } else if constexpr (DEV) {
-      // plain sums of the deviations (FP32 storage)
+    if constexpr (DEV) {
+      // plain sums of the deviations; with 16-bit storage the energy moment
+      // may be summed term by term in FP64 instead (p.e64), a choice taken
+      // once per cell: tested per term, it is compiled into selects that
+      // compute both sums
       R sr = R(0), se = R(0), sg = R(0);
-      static_for<Q>([&](auto qc) {
-        constexpr int q = decltype(qc)::value;
-        const R d = ft[q][r];
-        sr += d;
-        if constexpr (S::moves(q, 0)) jx = fma(R(S::xh(q, 0)), d, jx);
-        if constexpr (S::moves(q, 1)) jy = fma(R(S::xh(q, 1)), d, jy);
-        if constexpr (D == 3 && S::moves(q, 2)) jz = fma(R(S::xh(q, 2)), d, jz);
-        if constexpr (COMP) {
-          constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
-          if constexpr (X != 0.0) se = fma(R(X), d, se);
-          sg += ft[Q + q][r];
-        }
-      });
+      auto sums = [&](auto e64c) {
+        constexpr bool E64 = decltype(e64c)::value;
+        static_for<Q>([&](auto qc) {
+          constexpr int q = decltype(qc)::value;
+          const R d = ft[q][r];
+          sr += d;
+          if constexpr (S::moves(q, 0)) jx = fma(R(S::xh(q, 0)), d, jx);
+          if constexpr (S::moves(q, 1)) jy = fma(R(S::xh(q, 1)), d, jy);
+          if constexpr (D == 3 && S::moves(q, 2)) jz = fma(R(S::xh(q, 2)), d, jz);
+          if constexpr (COMP) {
+            constexpr double X = S::xh(q, 0) * S::xh(q, 0) + S::xh(q, 1) * S::xh(q, 1) + S::xh(q, 2) * S::xh(q, 2);
+            if constexpr (X != 0.0) {
+              if constexpr (E64) Ed = fma(X, double(d), Ed);
+              else se = fma(R(X), d, se);
+            }
+            sg += ft[Q + q][r];
+          }
+        });
+      };
+      if constexpr (TR::coarse && COMP) {
+        if (p.e64 != 0.0) sums(std::true_type{});
+        else sums(std::false_type{});
+      } else {
+        sums(std::false_type{});
+      }
       drho = R(p.sw - 1.0) + sr;
       rho = R(p.sw) + sr;
       jx += R(p.swx[0]);
       jy += R(p.swx[1]);
       jz += R(p.swx[2]);
       if constexpr (COMP) {
+        // (se = 0 when Ed holds the FP64 sum, Ed = 0 otherwise)
+        Ed += double(se);
+        Epre64 = Ed + double(sg);
         Epre = se + sg;
-        Epre64 = double(se) + double(sg);
-        Ed = p.swX + double(se);
+        Ed += p.swX;
         Ef = R(p.swX) + se;
         G = R(p.cv2mD * p.sw) + sg;
       }
@@ -1517,7 +1496,7 @@ void sl_kernel(KParams p) {
     // (sum_i w_i = 1 up to d0), and its energy cM sum_i w_i |xh_i|^2 counted in
     // the energy balance after the small residual E_pre - E_eq has formed (added
     // to the accumulator first it would fall below half an ulp of its terms).
-    constexpr bool EFIX = COMP && DEV && !TR::kahan;
+    constexpr bool EFIX = COMP && DEV && !TR::coarse;
     R Eeq[RO], cM[RO];
     double Eeq64[RO];
 #pragma unroll
