@@ -75,9 +75,9 @@ hipError_t launch_step(const KParams& p, hipStream_t s) {
     // tiles one cell thick along z (RO = 1): bricks when the XCD's xy plane
     // of tiles is larger than half the blocks it holds at once (sl_kernel).
     // Measured on D3Q45 f + g at 256^3: FP64 15 % faster than the x, y, z
-    // order (11.75 against 13.79 ms), FP32 within 2 %; with two cells per
-    // thread (the 16-bit kernels) the x, y, z order reads less (2.6x the
-    // state against 3.9x) and runs 2 % faster, so they keep it.
+    // order (11.75 against 13.79 ms); with two cells per thread (the FP32 and
+    // 16-bit kernels) the x, y, z order reads less (16-bit: 2.6x the state
+    // against 3.9x) and runs 2 % faster, so they keep it.
     const int window = per_cu * (p.cus > 0 ? p.cus / 8 : 32);
     if (RO == 1 && 2 * q.tiles[0] * q.rsy > window) {
       q.bz = std::min(q.rsz, 16);

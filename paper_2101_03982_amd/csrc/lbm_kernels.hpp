@@ -298,11 +298,16 @@ constexpr int cells_per_thread() {
   // 2D grids are small (512^2 = 2^18 cells): two cells per thread for the
   // f + g sets keeps more than two blocks per compute unit
   if (D == 2) return vals <= 30 ? 4 : (vals <= 80 ? 2 : 1);
-  // 16-bit storage halves the bytes per value: its kernels keep two cells per
-  // thread (fewer halo re-reads; measured faster at 256^3 than one cell at
-  // higher occupancy)
-  if (ST == ST_BF16 || ST == ST_F16) return vals <= 30 ? 4 : (vals <= 90 ? 2 : 1);
-  return vals <= 30 ? 4 : (vals <= 60 ? 2 : 1);
+  // FP64 holds a value in two registers
+  if (ST == ST_F64) return vals <= 30 ? 4 : (vals <= 60 ? 2 : 1);
+  // the quasi-equilibrium step's FP32 f + g kernels: one cell per thread (its
+  // heat fluxes take two cells past 256 registers, one wave per SIMD: D3Q45
+  // 7.68 against 7.3 ms at 256^3)
+  if (MODE == MODE_STEP_QE && ST == ST_F32 && vals > 60) return 1;
+  // two cells per thread up to 90 values, the D3Q45 f + g kernels included:
+  // fewer halo re-reads, measured faster at 256^3 than one cell per thread at
+  // higher occupancy (FP32 5.56 against 7.16 ms)
+  return vals <= 30 ? 4 : (vals <= 90 ? 2 : 1);
 }
 
 // Node index on the grid: periodic wrap (valid for i in [-n, 2n)) or, on an
@@ -329,7 +334,8 @@ struct Tile {
   // waves per block: eight (a 64x8xRO tile, less y halo per cell) where two
   // such blocks still fit on a compute unit and measured faster: the 17-21
   // velocity sets (3 %) and the FP32 f + g kernels with one cell per thread
-  // (5-7 %); four elsewhere
+  // (5-7 %); four elsewhere (the D3Q45 f + g kernels with two cells: 64x8x2
+  // measured 9 % slower than 64x4x2 in FP32, 14-15 % in 16-bit)
   // (cell-wise support: four, a whole number of cells)
   static constexpr int NW =
       (!Support<NS>::glc && ((D == 3 && A == 1 && RO == 4 && S::Q > 16 && S::Q <= 21) ||
@@ -1086,8 +1092,9 @@ constexpr int sl_threads() {
 }
 
 // Minimum waves per SIMD the register allocation must allow: four for the
-// FP32 f + g kernels (two 8-wave blocks per compute unit; a few spilled
-// registers cost less than the lost occupancy, measured 5-7 %), else no bound.
+// FP32 f + g kernels with one cell per thread (two 8-wave blocks per compute
+// unit; a few spilled registers cost less than the lost occupancy, measured
+// 5-7 %), else no bound.
 template <int SET, int NS, int A, int ST, int MODE>
 constexpr int sl_min_waves() {
   return (Set<SET>::D == 3 && A == 2 && ST == ST_F32 && is_step(MODE) &&
@@ -1109,6 +1116,9 @@ void sl_kernel(KParams p) {
   constexpr int Q = S::Q;
   constexpr bool DEV = TR::dev;
   constexpr bool COMP = (A == 2);
+  // the energy moment summed in FP64 (16-bit compressible storage only; the
+  // host rejects it elsewhere, so other kernels carry none of its code)
+  constexpr bool E64 = TR::coarse && COMP;
   constexpr int RO = cells_per_thread<D, Q, A, ST, MODE>();
   using TL = Tile<SET, NS, A, ST, RO>;
 
@@ -1323,7 +1333,7 @@ void sl_kernel(KParams p) {
           }
         });
       };
-      if constexpr (TR::coarse && COMP) {
+      if constexpr (E64) {
         if (p.e64 != 0.0) sums(std::true_type{});
         else sums(std::false_type{});
       } else {
@@ -1395,7 +1405,7 @@ void sl_kernel(KParams p) {
           // is formed from small quantities (no cancellation against 2 C_v)
           const double twocv = 1.0 / p.inv2cv;
           const double e0 = p.swX + p.cv2mD * p.sw - twocv;  // zero up to rounding of the table sums
-          if (p.e64 != 0.0) {
+          if (E64 && p.e64 != 0.0) {
             const double et = (Epre64 + e0 - double(rho) * double(U) - twocv * double(drho)) * p.inv2cv / double(rho);
             eta = R(et);
             theta = R(1.0 + et);
@@ -1498,11 +1508,9 @@ void sl_kernel(KParams p) {
     // to the accumulator first it would fall below half an ulp of its terms).
     constexpr bool EFIX = COMP && DEV && !TR::coarse;
     R Eeq[RO], cM[RO];
-    double Eeq64[RO];
 #pragma unroll
     for (int r = 0; r < RO; ++r) {
       Eeq[r] = R(0);
-      Eeq64[r] = 0.0;
       cM[r] = R(0);
       if constexpr (EFIX) {
         const Mom& m = mc[r];
@@ -1548,7 +1556,6 @@ void sl_kernel(KParams p) {
           if constexpr (EFIX) {
             if constexpr (X != 0.0) Eeq[r] = fma(R(X), feq_dev, Eeq[r]);
             Eeq[r] += geq;
-            if (p.e64 != 0.0) Eeq64[r] += X * double(feq_dev) + double(geq);
             ft[q][r] = geq - ft[Q + q][r];  // f_q is stored: its register keeps g^eq - g
           } else {
             R go = fma(m.omega, geq - ft[Q + q][r], ft[Q + q][r]);
@@ -1563,7 +1570,6 @@ void sl_kernel(KParams p) {
 #pragma unroll
       for (int r = 0; r < RO; ++r) {
         cE[r] = ((mc[r].Epre - Eeq[r]) - cM[r] * R(p.swX)) * R(1.0 / p.sw);
-        if (p.e64 != 0.0) cE[r] = R(((mc[r].Epre64 - Eeq64[r]) - double(cM[r]) * p.swX) / p.sw);
       }
       static_for<Q>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
