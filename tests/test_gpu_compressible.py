@@ -139,8 +139,8 @@ def test_reduced_precision_one_step(orc, storage, Ma, e64):
 
 @pytest.mark.parametrize("Ma", [0.5, 1.0])
 def test_compressible_fp32_parity_ragged(orc, Ma):
-    """FP32 f + g storage (eight-wave blocks, one cell per thread) on a grid
-    with a ragged tail on every axis, random fields with theta != 1: three
+    """FP32 f + g storage (64 x 4 x 2 tiles) on a grid with a ragged tail on
+    the x and y axes, random fields with theta != 1: three
     steps within 1.5e-5 of the oracle, relative to each population's own
     largest deviation from its reference value (measured <= 5.8e-6)."""
     base = W.ctgv_workload(n=16, Ma=Ma)
@@ -152,6 +152,36 @@ def test_compressible_fp32_parity_ragged(orc, Ma):
     lat.step(3)
     f = orc.run(cfg, f, 3)
     check(lat, gpu_populations(lat), f, "f32", 1.5e-5, "ctgv_ragged_Ma%.1f" % Ma)
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
+def test_compressible_two_cell_tiles_odd_z(orc, storage):
+    """The FP32 and 16-bit D3Q45 f + g step kernels hold two cells per thread
+    along z (64 x 4 x 2 tiles): a grid with nz odd ends in a half-filled tile,
+    ragged along x and y too (66 x 7 x 9), random fields with theta != 1.
+    Two steps: FP32 within 1.5e-5 of each population's largest deviation
+    (as the ragged test above); 16-bit one step within three of its ulps of
+    that deviation, plus 2^-23 for FP16's subnormal range."""
+    base = W.ctgv_workload(n=16, Ma=1.0)
+    wl = base.with_(grid=(66, 7, 9))
+    lat, cfg = pair(orc, "D3Q45", wl.grid, wl.tau, 4, wl.stencil, storage, wl.dx, wl.dt, wl.cs,
+                    compressible=True, gamma=wl.gamma)
+    rho, u, theta = W.random_fields(3, cfg.shape, 5, u_amp=0.3 * wl.cs, rho_amp=0.05, theta_amp=0.05)
+    f = init_both(lat, orc, cfg, rho, u, theta)
+    steps = 2 if storage == "f32" else 1
+    lat.step(steps)
+    f = orc.run(cfg, f, steps)
+    got = gpu_populations(lat)
+    if storage == "f32":
+        check(lat, got, f, "f32", 1.5e-5, "ctgv_odd_z_f32")
+        return
+    w = np.array(lat.table()["w"])
+    Cv = 1.0 / (wl.gamma - 1.0)
+    ref = np.concatenate([w, (2 * Cv - 3) * w]).reshape((-1, 1, 1, 1))
+    scale = np.max(np.abs(f - ref), axis=(1, 2, 3), keepdims=True)
+    tol = 3 * ULP[storage] * scale + 2.0 ** -23
+    note("ctgv_odd_z_%s" % storage, err=float(np.max(np.abs(got - f) / tol)))
+    assert np.all(np.abs(got - f) <= tol), float(np.max(np.abs(got - f) / tol))
 
 
 @pytest.mark.parametrize("storage", ["f32", "bf16", "f16"])
