@@ -300,10 +300,6 @@ constexpr int cells_per_thread() {
   if (D == 2) return vals <= 30 ? 4 : (vals <= 80 ? 2 : 1);
   // FP64 holds a value in two registers
   if (ST == ST_F64) return vals <= 30 ? 4 : (vals <= 60 ? 2 : 1);
-  // the quasi-equilibrium step's FP32 f + g kernels: one cell per thread (its
-  // heat fluxes take two cells past 256 registers, one wave per SIMD: D3Q45
-  // 7.68 against 7.3 ms at 256^3)
-  if (MODE == MODE_STEP_QE && ST == ST_F32 && vals > 60) return 1;
   // two cells per thread up to 90 values, the D3Q45 f + g kernels included:
   // fewer halo re-reads, measured faster at 256^3 than one cell per thread at
   // higher occupancy (FP32 5.56 against 7.16 ms)
@@ -333,14 +329,11 @@ struct Tile {
   static constexpr int TX = 64;
   // waves per block: eight (a 64x8xRO tile, less y halo per cell) where two
   // such blocks still fit on a compute unit and measured faster: the 17-21
-  // velocity sets (3 %) and the FP32 f + g kernels with one cell per thread
-  // (5-7 %); four elsewhere (the D3Q45 f + g kernels with two cells: 64x8x2
+  // velocity sets (3 %); four elsewhere (the D3Q45 f + g kernels: 64x8x2
   // measured 9 % slower than 64x4x2 in FP32, 14-15 % in 16-bit)
   // (cell-wise support: four, a whole number of cells)
   static constexpr int NW =
-      (!Support<NS>::glc && ((D == 3 && A == 1 && RO == 4 && S::Q > 16 && S::Q <= 21) ||
-                             (D == 3 && A == 2 && RO == 1 && ST == ST_F32)))
-          ? 8 : 4;
+      (!Support<NS>::glc && D == 3 && A == 1 && RO == 4 && S::Q > 16 && S::Q <= 21) ? 8 : 4;
   static constexpr int NT = 64 * NW;                 // threads per block
   static constexpr int H = Support<NS>::halo;
   static constexpr int PX = TX + ((H + 2) & ~1);     // widest LDS row (even: pairs of x)
@@ -1091,14 +1084,13 @@ constexpr int sl_threads() {
   return Tile<SET, NS, A, ST, cells_per_thread<Set<SET>::D, Set<SET>::Q, A, ST, MODE>()>::NT;
 }
 
-// Minimum waves per SIMD the register allocation must allow: four for the
-// FP32 f + g kernels with one cell per thread (two 8-wave blocks per compute
-// unit; a few spilled registers cost less than the lost occupancy, measured
-// 5-7 %), else no bound.
+// Minimum waves per SIMD the register allocation must allow: two for the
+// FP32 quasi-equilibrium f + g step in 3D (two cells per thread; its heat
+// fluxes would take it to 273 registers, one wave per SIMD: 17 spilled
+// registers cost less, D3Q45 at 256^3 5.92 against 7.68 ms), else no bound.
 template <int SET, int NS, int A, int ST, int MODE>
 constexpr int sl_min_waves() {
-  return (Set<SET>::D == 3 && A == 2 && ST == ST_F32 && is_step(MODE) &&
-          cells_per_thread<Set<SET>::D, Set<SET>::Q, A, ST, MODE>() == 1) ? 4 : 1;
+  return (Set<SET>::D == 3 && A == 2 && ST == ST_F32 && MODE == MODE_STEP_QE) ? 2 : 1;
 }
 
 // CP: cache policy of the result stores (0 or CP_STREAM).  XP: x pairs
