@@ -1,10 +1,12 @@
 // Enstrophy E = <|curl u|^2> of a velocity field on the uniform periodic grid
 // (the diagnostic of Sec. 4.2), by central differences:
 //   d f / d x_a (x) ~ sum_{j=1..m} c_j (f(x + j e_a) - f(x - j e_a)) / dx.
-// 3D: tiles marching along z (register window for z, LDS plane for x and y);
+// 3D: one node per thread, neighbours read through the caches;
 // 2D: one wave per grid row.  FP64 arithmetic on the loaded values,
 // block sums in a fixed tree order, then one block adds the block sums in
 // index order: the result does not depend on scheduling.
+#include <algorithm>
+
 #include "lbm_diag.hpp"
 
 namespace lbm {
@@ -74,15 +76,14 @@ __global__ __launch_bounds__(DIAG_THREADS) void enstrophy2d_kernel(CurlParams p)
   if (threadIdx.x == 0) p.partial[blockIdx.x] = red[0];
 }
 
-// 3D: a 64 x 4 (x, y) tile marching through ZT_Z planes of z (4: enough
-// blocks to fill the chip at 128^3; measured faster than 8 or 16).  The z
-// derivatives come from a window of 2M + 1 planes kept in registers per
-// thread (u_x, u_y); the x and y derivatives from one plane staged in LDS with
-// its halo (u_x with a y halo, u_y with an x halo, u_z with both).  About ten
-// loads per node instead of the 12 M of the row kernel.  Every load index is
-// wrapped onto the periodic grid; lanes past a ragged edge load wrapped
-// nodes and add nothing.
-constexpr int ZT_X = 64, ZT_Y = DIAG_WAVES, ZT_Z = 4;
+// 3D: one node per thread, 64 x 4 (x, y) tiles of one z plane, every
+// neighbour read straight from global memory through the caches (8 M loads
+// per node, re-read from L1 and L2; nothing waits on a barrier).  Lanes past
+// a ragged edge load nothing.  FP32 at 128^3: 34.6 us with 32-bit indices,
+// 46.6 us with 64-bit ones, against 61.0 us for tiles marching along z with
+// LDS planes and a register window along z (their loads waited on the
+// tile's barriers).
+constexpr int ZT_X = 64, ZT_Y = DIAG_WAVES;
 
 __device__ inline int64_t wrap_any(int64_t i, int64_t N) {
   if (i >= 0 && i < N) return i;
@@ -90,79 +91,53 @@ __device__ inline int64_t wrap_any(int64_t i, int64_t N) {
   return i < 0 ? i + N : i;
 }
 
-template <typename R, int M>
+// i + d on a periodic line of N nodes, |d| <= MAX_HALF_WIDTH, i in [0, N):
+// one add or subtract of N unless the line is shorter than the stencil
+template <typename I>
+__device__ inline I wrap_near(I i, int d, I N) {
+  I k = i + d;
+  k += (k < 0) ? N : 0;
+  k -= (k >= N) ? N : 0;
+  return (k >= 0 && k < N) ? k : I(wrap_any(k, N));
+}
+
+// I: the index type, 32-bit when all three components hold fewer than 2^31
+// elements (the host's choice), else 64-bit
+template <typename R, int M, typename I>
 __global__ __launch_bounds__(DIAG_THREADS) void enstrophy3d_kernel(CurlParams p) {
   const R* u = static_cast<const R*>(p.u);
   const R* ux = u;
   const R* uy = u + p.ncell;
   const R* uz = u + 2 * p.ncell;
-  const int64_t nx = p.n[0], ny = p.n[1], nz = p.n[2], nxy = nx * ny;
-  const int64_t tiles_x = (nx + ZT_X - 1) / ZT_X, tiles_y = (ny + ZT_Y - 1) / ZT_Y;
-  const int64_t tiles = tiles_x * tiles_y * ((nz + ZT_Z - 1) / ZT_Z);
+  const I nx = I(p.n[0]), ny = I(p.n[1]), nz = I(p.n[2]);
+  const I tiles_x = (nx + ZT_X - 1) / ZT_X, tiles_y = (ny + ZT_Y - 1) / ZT_Y;
+  const int64_t tiles = int64_t(tiles_x) * tiles_y * nz;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  __shared__ R sx[ZT_Y + 2 * M][ZT_X];          // u_x, rows y - M .. y + 3 + M
-  __shared__ R sy[ZT_Y][ZT_X + 2 * M];          // u_y, columns x - M .. x + 63 + M
-  __shared__ R sz[ZT_Y + 2 * M][ZT_X + 2 * M];  // u_z, both halos
   double c[M];
 #pragma unroll
   for (int j = 0; j < M; ++j) c[j] = p.c[j];
   double acc = 0.0;
   for (int64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-    const int64_t tx = t % tiles_x, ty = (t / tiles_x) % tiles_y, tz = t / (tiles_x * tiles_y);
-    const int64_t x0 = tx * ZT_X, y0 = ty * ZT_Y, z0 = tz * ZT_Z;
-    const int64_t z1 = (z0 + ZT_Z < nz) ? z0 + ZT_Z : nz;
-    const bool valid = (x0 + lane < nx) && (y0 + wv < ny);
-    const int64_t col = wrap_any(y0 + wv, ny) * nx + wrap_any(x0 + lane, nx);  // (x, y) of this thread
-    // window: w[k] = u(z + k - M), k = 0 .. 2M; the last slot is loaded per plane
-    R wx[2 * M + 1], wy[2 * M + 1];
+    const I tt = I(t), tx = tt % tiles_x, ty = (tt / tiles_x) % tiles_y, z = tt / (tiles_x * tiles_y);
+    const I x = tx * ZT_X + lane, y = ty * ZT_Y + wv;
+    if (x >= nx || y >= ny) continue;
+    const I row = (z * ny + y) * nx;  // node (0, y, z)
+    double dxuy = 0, dxuz = 0, dyux = 0, dyuz = 0, dzux = 0, dzuy = 0;
 #pragma unroll
-    for (int k = 0; k < 2 * M; ++k) {
-      const int64_t e = wrap_any(z0 + k - M, nz) * nxy + col;
-      wx[k] = ux[e];
-      wy[k] = uy[e];
+    for (int j = 1; j <= M; ++j) {
+      const double cj = c[j - 1];
+      const I xp = row + wrap_near(x, j, nx), xm = row + wrap_near(x, -j, nx);
+      const I yp = (z * ny + wrap_near(y, j, ny)) * nx + x, ym = (z * ny + wrap_near(y, -j, ny)) * nx + x;
+      const I zp = (wrap_near(z, j, nz) * ny + y) * nx + x, zm = (wrap_near(z, -j, nz) * ny + y) * nx + x;
+      dxuy = fma(cj, double(uy[xp]) - double(uy[xm]), dxuy);
+      dxuz = fma(cj, double(uz[xp]) - double(uz[xm]), dxuz);
+      dyux = fma(cj, double(ux[yp]) - double(ux[ym]), dyux);
+      dyuz = fma(cj, double(uz[yp]) - double(uz[ym]), dyuz);
+      dzux = fma(cj, double(ux[zp]) - double(ux[zm]), dzux);
+      dzuy = fma(cj, double(uy[zp]) - double(uy[zm]), dzuy);
     }
-    for (int64_t z = z0; z < z1; ++z) {
-      const int64_t plane = z * nxy;
-      {
-        const int64_t e = wrap_any(z + M, nz) * nxy + col;
-        wx[2 * M] = ux[e];
-        wy[2 * M] = uy[e];
-      }
-      __syncthreads();  // the previous plane's reads of the LDS buffers are done
-      for (int i = threadIdx.x; i < (ZT_Y + 2 * M) * ZT_X; i += DIAG_THREADS) {
-        const int r = i / ZT_X, q = i % ZT_X;
-        sx[r][q] = ux[plane + wrap_any(y0 + r - M, ny) * nx + wrap_any(x0 + q, nx)];
-      }
-      for (int i = threadIdx.x; i < ZT_Y * (ZT_X + 2 * M); i += DIAG_THREADS) {
-        const int r = i / (ZT_X + 2 * M), q = i % (ZT_X + 2 * M);
-        sy[r][q] = uy[plane + wrap_any(y0 + r, ny) * nx + wrap_any(x0 + q - M, nx)];
-      }
-      for (int i = threadIdx.x; i < (ZT_Y + 2 * M) * (ZT_X + 2 * M); i += DIAG_THREADS) {
-        const int r = i / (ZT_X + 2 * M), q = i % (ZT_X + 2 * M);
-        sz[r][q] = uz[plane + wrap_any(y0 + r - M, ny) * nx + wrap_any(x0 + q - M, nx)];
-      }
-      __syncthreads();
-      double dxuy = 0, dxuz = 0, dyux = 0, dyuz = 0, dzux = 0, dzuy = 0;
-#pragma unroll
-      for (int j = 1; j <= M; ++j) {
-        const double cj = c[j - 1];
-        dxuy = fma(cj, double(sy[wv][lane + M + j]) - double(sy[wv][lane + M - j]), dxuy);
-        dxuz = fma(cj, double(sz[wv + M][lane + M + j]) - double(sz[wv + M][lane + M - j]), dxuz);
-        dyux = fma(cj, double(sx[wv + M + j][lane]) - double(sx[wv + M - j][lane]), dyux);
-        dyuz = fma(cj, double(sz[wv + M + j][lane + M]) - double(sz[wv + M - j][lane + M]), dyuz);
-        dzux = fma(cj, double(wx[M + j]) - double(wx[M - j]), dzux);
-        dzuy = fma(cj, double(wy[M + j]) - double(wy[M - j]), dzuy);
-      }
-      if (valid) {
-        const double ox = dyuz - dzuy, oy = dzux - dxuz, oz = dxuy - dyux;
-        acc += ox * ox + oy * oy + oz * oz;
-      }
-#pragma unroll
-      for (int k = 0; k < 2 * M; ++k) {
-        wx[k] = wx[k + 1];
-        wy[k] = wy[k + 1];
-      }
-    }
+    const double ox = dyuz - dzuy, oy = dzux - dxuz, oz = dxuy - dyux;
+    acc += ox * ox + oy * oy + oz * oz;
   }
   __shared__ double red[DIAG_THREADS];
   red[threadIdx.x] = acc;
@@ -174,14 +149,23 @@ __global__ __launch_bounds__(DIAG_THREADS) void enstrophy3d_kernel(CurlParams p)
   if (threadIdx.x == 0) p.partial[blockIdx.x] = red[0];
 }
 
+template <typename R, typename I>
+void launch_3d_idx(const CurlParams& p, int blocks, hipStream_t s) {
+  switch (p.m) {
+    case 1: hipLaunchKernelGGL((enstrophy3d_kernel<R, 1, I>), dim3(blocks), dim3(DIAG_THREADS), 0, s, p); break;
+    case 2: hipLaunchKernelGGL((enstrophy3d_kernel<R, 2, I>), dim3(blocks), dim3(DIAG_THREADS), 0, s, p); break;
+    case 3: hipLaunchKernelGGL((enstrophy3d_kernel<R, 3, I>), dim3(blocks), dim3(DIAG_THREADS), 0, s, p); break;
+    default: hipLaunchKernelGGL((enstrophy3d_kernel<R, 4, I>), dim3(blocks), dim3(DIAG_THREADS), 0, s, p); break;
+  }
+}
+
 template <typename R>
 void launch_3d(const CurlParams& p, int blocks, hipStream_t s) {
-  switch (p.m) {
-    case 1: hipLaunchKernelGGL((enstrophy3d_kernel<R, 1>), dim3(blocks), dim3(DIAG_THREADS), 0, s, p); break;
-    case 2: hipLaunchKernelGGL((enstrophy3d_kernel<R, 2>), dim3(blocks), dim3(DIAG_THREADS), 0, s, p); break;
-    case 3: hipLaunchKernelGGL((enstrophy3d_kernel<R, 3>), dim3(blocks), dim3(DIAG_THREADS), 0, s, p); break;
-    default: hipLaunchKernelGGL((enstrophy3d_kernel<R, 4>), dim3(blocks), dim3(DIAG_THREADS), 0, s, p); break;
-  }
+  const int64_t tiles = ((p.n[0] + ZT_X - 1) / ZT_X) * ((p.n[1] + ZT_Y - 1) / ZT_Y) * p.n[2];
+  if (3 * p.ncell < (int64_t(1) << 31) && tiles < (int64_t(1) << 31))
+    launch_3d_idx<R, int32_t>(p, blocks, s);
+  else
+    launch_3d_idx<R, int64_t>(p, blocks, s);
 }
 
 __global__ __launch_bounds__(DIAG_THREADS) void sum_blocks_kernel(const double* partial, int nblocks, double* out) {
@@ -209,8 +193,11 @@ hipError_t launch_enstrophy(const void* u, bool f64, const int64_t n[3], int D, 
   p.m = m;
   for (int j = 0; j < m; ++j) p.c[j] = coef[j];
   p.partial = partial;
-  // 3D: one block per tile of the z-marching kernel; 2D: one wave per row
-  const int64_t want = (D == 3) ? ((n[0] + ZT_X - 1) / ZT_X) * ((n[1] + ZT_Y - 1) / ZT_Y) * ((n[2] + ZT_Z - 1) / ZT_Z)
+  // 3D: one block per (x, y) tile of a plane, up to eight blocks per compute
+  // unit (2048; then each block takes every 2048th tile: the single-block
+  // sum of 8192 partials at 128^3 took 9.9 us against 5 us); 2D: one wave
+  // per row
+  const int64_t want = (D == 3) ? std::min<int64_t>(((n[0] + ZT_X - 1) / ZT_X) * ((n[1] + ZT_Y - 1) / ZT_Y) * n[2], 2048)
                                 : (n[1] * n[2] + DIAG_WAVES - 1) / DIAG_WAVES;
   const int blocks = want < 1 ? 1 : int(want < max_blocks ? want : max_blocks);
   if (f64) {
