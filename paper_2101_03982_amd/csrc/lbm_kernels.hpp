@@ -263,6 +263,7 @@ struct KParams {
   int tiles[3];        // tiles along x, y (3D) / outer (2D), z (3D)
   int chunk;           // tiles per XCD
   int rsy, rsz;        // 3D: y and z tiles of each XCD's block of the grid (0: linear order)
+  int ysl;             // 3D: log2 of the XCD blocks along y (1: 2 x 4 (y, z) blocks, 2: 4 x 2)
   int by, bz;          // 3D brick order: bricks of by x bz (y, z) tiles (0: x, y, z order)
   int cus;             // compute units of the device (host input: sizes the brick order)
   double omega;        // 1 / tau (weakly compressible)
@@ -1131,8 +1132,9 @@ void sl_kernel(KParams p) {
   g.nx = p.n[0];
   g.bcx = p.bc[0];
   // XCD-aware tile order: hardware blocks go round-robin to the 8 XCDs.  Each
-  // XCD gets one block of the grid (3D: a 2 x 4 split of the y and z tiles,
-  // so that the halo planes two XCDs both read are few).  The XCD walks it so
+  // XCD gets one block of the grid (3D: a 4 x 2 or 2 x 4 split of the y and
+  // z tiles, the host's choice, so that the halo planes two XCDs both read
+  // are few).  The XCD walks it so
   // that the tiles it holds at once, which read each other's halo rows, are
   // neighbours: x, y, z when its xy plane of tiles is small against the
   // blocks it runs at once (the z neighbours then run together too); else in
@@ -1160,8 +1162,8 @@ void sl_kernel(KParams p) {
       ly = rest % p.rsy;
       lz = rest / p.rsy;
     }
-    tiy = (xcd & 1) * p.rsy + ly;
-    tiz = (xcd >> 1) * p.rsz + lz;
+    tiy = (xcd & ((1 << p.ysl) - 1)) * p.rsy + ly;
+    tiz = (xcd >> p.ysl) * p.rsz + lz;
     if (lz >= p.rsz || tiy >= p.tiles[1] || tiz >= p.tiles[2]) return;
   } else {
     const int tile = xcd * p.chunk + lt;
